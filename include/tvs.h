@@ -1,0 +1,167 @@
+/*
+ * libtvs -- TV-Stokes denoising by dual (Chambolle-type) iterations inside an
+ * overlapping Schwarz decomposition, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Langer, Runft, Rahman, Tai and Wu, "Functional
+ * Analysis and Parallel Domain Decomposition for the TV-Stokes Model"
+ * (arXiv 2602.17494):
+ *   Step 1 (tangent field smoothing, TFS): the dual problem eq. tfsdualdis,
+ *     min_{|p_k| <= 1} || P_K vecdiv p - delta^{-1} P_K tau_0 ||^2 on the
+ *     extended grid Omega-tilde, solved by Algorithm 1 (alg:chambTfs), and
+ *     tau = P_K tau_0 - delta P_K vecdiv p (Corollary Cor:tfsdual with
+ *     eq. tfs_dualPK);
+ *   Step 2 (image reconstruction, IRV2 of Section 3.3): the dual problem
+ *     eq. ir2dualdis, min_{|p| <= 1} || div p - alpha (d0 - g) ||^2 on Omega
+ *     with (D^-_x, D^-_y) g = (R_Omega tau)^perp, solved by Chambolle's
+ *     iteration, and d = d0 - div p / alpha;  IRV1 (eq. ir1dualdis with
+ *     eq. eq:defXi2:discrete and eq. eq:tau_hat) is available as a variant;
+ *   both inside the parallel overlapping Schwarz iteration of Algorithm 2
+ *     (alg:disalgsubsp) with the subdomain loops of Algorithm 3
+ *     (alg:tfsparinner, Step 2) and Algorithm 5 (alg:tfsparinnertfsloc,
+ *     Step 1, with the projection of locally supported data restricted to
+ *     the subdomain, eqs. locglobprojpart1 and locglobprojpart3).
+ *
+ * Grids, layout and ownership
+ *   The image grid Omega has N2 rows (y) and N1 columns (x), N2, N1 >= 2.
+ *   The Step-1 grid Omega-tilde has (N2+1) x (N1+1) points and holds Omega as
+ *   its first N2 rows and N1 columns (Section 4.1).  Arrays are row-major:
+ *     image  d0, d      : N2 * N1 values
+ *     field  tau        : 2 planes of (N2+1) * (N1+1) values, plane 0 = tau_1
+ *                         (x-component), plane 1 = tau_2 (y-component)
+ *   All array pointers are DEVICE pointers owned by the caller, of the element
+ *   type given by `dtype` (float or double).  The library owns only its
+ *   context, the per-problem plans and work buffers it caches inside the
+ *   context, all released by tvs_ctx_destroy.
+ *
+ * Streams
+ *   `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Work is enqueued on it in order.  When `stats` is non-NULL the call
+ *   waits for the stream before returning (it reads FP64 reductions back);
+ *   otherwise outputs are valid once the stream has been synchronised.  Calls
+ *   sharing one context must not overlap (the context's work buffers are
+ *   reused); use one context per concurrent caller.
+ *
+ * Errors
+ *   Every call returns TVS_OK (0) or a negative code; tvs_last_error()
+ *   returns a thread-local message for the last failure.  No C++ exception
+ *   crosses this interface.
+ */
+#ifndef TVS_H_
+#define TVS_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TVS_OK = 0,
+  TVS_EINVAL = -1,    /* shape, parameter or layout out of range */
+  TVS_ENOMEM = -2,    /* device allocation failed */
+  TVS_EHIP = -3,      /* a HIP runtime call or kernel launch failed */
+  TVS_ENONFINITE = -4 /* an FP64 reduction found NaN or Inf */
+};
+
+typedef enum { TVS_F32 = 0, TVS_F64 = 1 } tvs_dtype;
+
+/* Step-2 reconstruction variant (Section 5.1). */
+typedef enum { TVS_IRV2 = 0, TVS_IRV1 = 1 } tvs_variant;
+
+/* Model and iteration parameters.
+ *   delta  > 0      TFS weight (eq. eq:cTFS)
+ *   alpha  > 0      Step-2 weight (eq. modifiedStep2; IRV1: alpha = 1/mu)
+ *   t in (0, 1/8]   dual step size (Algorithm 1 and Theorem 3)
+ *   h      > 0      mesh size (the paper's experiments use h = 1)
+ *   eps    > 0      IRV1 smoothing of |tau^perp| (eq. eq:defXi2); unused by IRV2
+ *   variant         TVS_IRV2 or TVS_IRV1 */
+typedef struct {
+  double delta, alpha, t, h, eps;
+  int variant;
+} tvs_params;
+
+/* Subdomain layout (Section 6.1).  M2 x M1 subdomains (1 <= M <= 32 per
+ * axis); s_y, s_x = width of the stripe two neighbours share, centred on the
+ * core cut floor(k n / M) of the Omega-tilde axis (n = N+1); every core must
+ * be at least max(s, 2) points wide, and s >= 1 where M > 1.  The weights
+ * theta_m are linear ramps across the shared stripes.  alpha_hat <= 0 selects
+ * the colouring rule after Algorithm 2 (1, 1/2 or 1/4); otherwise it must lie
+ * in (0, 1].  M2 = M1 = 1 is the plain single-domain solve (theta = 1). */
+typedef struct {
+  int M2, M1, s_y, s_x;
+  double alpha_hat;
+} tvs_layout;
+
+/* Iteration counts: `sweeps` outer iterations of Algorithm 2 (>= 1), each
+ * with `inner` subdomain iterations (>= 1).  tol > 0 stops after the first
+ * sweep whose stopping residual (below) falls under tol; tol = 0 runs the
+ * fixed counts. */
+typedef struct {
+  int sweeps, inner;
+  double tol;
+} tvs_iters;
+
+/* FP64 results of one step, computed on the GPU:
+ *   energy    D(p) of the final iterate (eq. tfsdualdis / ir2dualdis)
+ *   residual  |D(p^{S-1})^{1/2} - D(p^S)^{1/2}| / (c |Gamma|)^{1/2} over the
+ *             last sweep (c = 2 channels for TFS, 1 otherwise): the left side
+ *             of the paper's stopping tests (Section 5.2) over their scale
+ *   gap       duality gap sum_k sum(|grad u_k| + grad u_k . p_k) of the final
+ *             iterate with its primal (tau for TFS, (f - div p)/alpha for
+ *             Step 2); >= 0 and 0 exactly at the solution
+ *   sweeps_done, seconds (host wall time of the call, including the wait). */
+typedef struct {
+  int sweeps_done;
+  double energy, gap, residual, seconds;
+} tvs_stats;
+
+typedef struct tvs_ctx tvs_ctx;
+
+/* Create a context on HIP device `device`.  Returns TVS_OK and *out. */
+int tvs_ctx_create(int device, tvs_ctx** out);
+/* Release the context and everything it cached.  NULL is ignored. */
+void tvs_ctx_destroy(tvs_ctx* ctx);
+/* Thread-local message of the last failing call ("" if none). */
+const char* tvs_last_error(void);
+/* Bytes of device memory the context currently holds (plans, work buffers). */
+size_t tvs_ctx_bytes(const tvs_ctx* ctx);
+
+/* Step 1 (TFS) from the observed image d0 (N2*N1) to the smoothed tangent
+ * field tau_out (2 planes of (N2+1)*(N1+1)): tau_0 = (-D^{neum-}_y d0,
+ * D^{neum-}_x d0) (eq. def:backdiffNeumann), f = delta^{-1} P_K tau_0, then
+ * Algorithm 2 on Omega-tilde with the localized inner loop of Algorithm 5,
+ * then tau = delta (f - P_K vecdiv p).  stats may be NULL. */
+int tvs_step1(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dtype,
+              const tvs_params* params, const tvs_layout* layout, const tvs_iters* iters,
+              void* tau_out, tvs_stats* stats, void* stream);
+
+/* Step 2 from d0 (N2*N1) and a tangent field tau (2 planes of
+ * (N2+1)*(N1+1)) to the image d_out (N2*N1).  IRV2: g = the row-wise
+ * integral of tau_2 on Omega (D^-_x g = tau_2 with the interior rule in every
+ * column, g = 0 left of the first column), f = alpha (d0 - g); IRV1:
+ * f = alpha d0 - div xi.  Then Algorithm 2 on Omega with the inner loop of
+ * Algorithm 3 (Lambda = div), and d = d0 - div p / alpha (IRV1: minus
+ * div xi / alpha as well).  stats may be NULL. */
+int tvs_step2(tvs_ctx* ctx, const void* d0, const void* tau, int N2, int N1, tvs_dtype dtype,
+              const tvs_params* params, const tvs_layout* layout, const tvs_iters* iters,
+              void* d_out, tvs_stats* stats, void* stream);
+
+/* Both steps with the same layout and counts.  tau_out may be NULL; stats,
+ * if not NULL, points to two entries (Step 1, Step 2). */
+int tvs_schwarz_solve(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dtype,
+                      const tvs_params* params, const tvs_layout* layout, const tvs_iters* iters,
+                      void* d_out, void* tau_out, tvs_stats* stats, void* stream);
+
+/* The orthogonal projection onto divergence-free fields of an n2 x n1 grid,
+ * P u = u - grad (Delta)^dagger div u (eq. formula:PKh, Proposition
+ * prop:DisProj), n2, n1 >= 3: u_in and u_out are 2 planes of n2*n1 (x- then
+ * y-component); they may alias.  Step 1 applies this operator on
+ * Omega-tilde. */
+int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dtype dtype,
+                         double h, void* u_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVS_H_ */

@@ -1,0 +1,530 @@
+// Image-method Neumann inverse Laplacian on boxes (see green.hpp).
+#include "green.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace tvs {
+
+// ---------------------------------------------------------------------------
+// FFT descriptors and twiddles (host)
+// ---------------------------------------------------------------------------
+static bool is_smooth(int n) {
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+int smooth_even_at_least(int n) {
+  int m = std::max(n, 2);
+  if (m & 1) ++m;
+  while (!is_smooth(m)) m += 2;
+  return m;
+}
+
+FftDesc make_fft_desc(int n) {
+  FftDesc d{};
+  d.n = n;
+  int m = n, k = 0;
+  while (m % 4 == 0) { d.radix[k++] = 4; m /= 4; }
+  while (m % 2 == 0) { d.radix[k++] = 2; m /= 2; }
+  while (m % 3 == 0) { d.radix[k++] = 3; m /= 3; }
+  while (m % 5 == 0) { d.radix[k++] = 5; m /= 5; }
+  if (m != 1 || k > kMaxPass) throw Error(-1, "FFT length " + std::to_string(n) + " is not 2^a 3^b 5^c");
+  d.npass = k;
+  return d;
+}
+
+template <typename T>
+static DevBuf make_twiddles(int n, hipStream_t s) {
+  std::vector<cplx<T>> h(n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int m = 0; m < n; ++m) {
+    const double a = two_pi * double(m) / double(n);
+    h[m] = cplx<T>{T(std::cos(a)), T(-std::sin(a))};
+  }
+  DevBuf d(sizeof(cplx<T>) * n);
+  TVS_HIP(hipMemcpyAsync(d.p, h.data(), sizeof(cplx<T>) * n, hipMemcpyHostToDevice, s));
+  TVS_HIP(hipStreamSynchronize(s));
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Torus kernel table (float64): G = C2^T (W C1) / (4 n2 n1)
+// ---------------------------------------------------------------------------
+
+// cos(pi k v / n) with the argument reduced exactly in integers
+__global__ void k_cos_table(double* c, int n) {
+  const int k = blockIdx.y;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += gridDim.x * blockDim.x) {
+    const long long m = (static_cast<long long>(k) * v) % (2LL * n);
+    c[static_cast<long long>(k) * (n + 1) + v] = cospi(static_cast<double>(m) / n);
+  }
+}
+
+// W[k2][k1] = c_k2 c_k1 / mu(k2, k1) with mu the eigenvalue of the periodic
+// 5-point Laplacian on the 2n2 x 2n1 torus, 0 for the constant mode, and
+// c_k = 1 at k = 0 and k = n, 2 otherwise (the cosine sum folds the torus
+// frequencies k and 2n - k together).
+__global__ void k_weight_table(double* w, int n2, int n1, double h) {
+  const int k2 = blockIdx.y;
+  const double s2 = sinpi(static_cast<double>(k2) / (2.0 * n2));
+  const double c2 = (k2 == 0 || k2 == n2) ? 1.0 : 2.0;
+  for (int k1 = blockIdx.x * blockDim.x + threadIdx.x; k1 <= n1; k1 += gridDim.x * blockDim.x) {
+    const double s1 = sinpi(static_cast<double>(k1) / (2.0 * n1));
+    const double c1 = (k1 == 0 || k1 == n1) ? 1.0 : 2.0;
+    const double lam = 4.0 * (s2 * s2 + s1 * s1) / (h * h);
+    w[static_cast<long long>(k2) * (n1 + 1) + k1] = (k2 == 0 && k1 == 0) ? 0.0 : -c2 * c1 / lam;
+  }
+}
+
+// out[i][j] = scale * sum_k A(i, k) B(k, j), A(i, k) = a[i * ai + k * ak],
+// B(k, j) = b[k * ldb + j]; 64 x 64 output tiles, 256 threads, 4 x 4 each.
+__global__ __launch_bounds__(256) void k_dgemm(const double* __restrict__ a, long long ai,
+                                               long long ak, const double* __restrict__ b,
+                                               long long ldb, double* __restrict__ out,
+                                               long long ldo, int M, int N, int K, double scale) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int kk = e / 64, ii = e % 64;
+      const int gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < M && gk < K) ? a[gi * ai + gk * ak] : 0.0;
+      const int gj = j0 + ii;
+      Bs[kk][ii] = (gk < K && gj < N) ? b[gk * ldb + gj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gi = i0 + ty + 16 * r, gj = j0 + tx + 16 * c;
+      if (gi < M && gj < N) out[gi * ldo + gj] = scale * acc[r][c];
+    }
+}
+
+GreenTable::GreenTable(int n2_, int n1_, double h_, hipStream_t s) : n2(n2_), n1(n1_), h(h_) {
+  const long long a2 = n2 + 1, a1 = n1 + 1;
+  DevBuf c1(sizeof(double) * a1 * a1), c2(sizeof(double) * a2 * a2);
+  DevBuf w(sizeof(double) * a2 * a1), t(sizeof(double) * a2 * a1);
+  g.alloc(sizeof(double) * a2 * a1);
+  hipLaunchKernelGGL(k_cos_table, dim3((a1 + 255) / 256, a1), dim3(256), 0, s, c1.as<double>(), n1);
+  TVS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_cos_table, dim3((a2 + 255) / 256, a2), dim3(256), 0, s, c2.as<double>(), n2);
+  TVS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_weight_table, dim3((a1 + 255) / 256, a2), dim3(256), 0, s, w.as<double>(),
+                     n2, n1, h);
+  TVS_LAUNCH_CHECK();
+  // T[k2][v] = sum_k1 W[k2][k1] C1[k1][v]
+  hipLaunchKernelGGL(k_dgemm, dim3((a1 + 63) / 64, (a2 + 63) / 64), dim3(256), 0, s,
+                     w.as<double>(), a1, 1LL, c1.as<double>(), a1, t.as<double>(), a1,
+                     int(a2), int(a1), int(a1), 1.0);
+  TVS_LAUNCH_CHECK();
+  // G[u][v] = sum_k2 C2[k2][u] T[k2][v] / (2 n2 * 2 n1)
+  hipLaunchKernelGGL(k_dgemm, dim3((a1 + 63) / 64, (a2 + 63) / 64), dim3(256), 0, s,
+                     c2.as<double>(), 1LL, a2, t.as<double>(), a1, g.as<double>(), a1, int(a2),
+                     int(a1), int(a2), 1.0 / (4.0 * double(n2) * double(n1)));
+  TVS_LAUNCH_CHECK();
+  TVS_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Window spectra (float64 build)
+// ---------------------------------------------------------------------------
+struct SlotKey {
+  int bi, bj, pi, pj;  // window base offsets; flip phase lengths (-1: none)
+  bool operator<(const SlotKey& o) const {
+    return std::tie(bi, bj, pi, pj) < std::tie(o.bi, o.bj, o.pi, o.pj);
+  }
+};
+
+__device__ __forceinline__ double g_lookup(const double* __restrict__ g, int n2, int n1, long long u,
+                                           long long v) {
+  const long long p2 = 2LL * n2, p1 = 2LL * n1;
+  u %= p2; if (u < 0) u += p2; if (u > n2) u = p2 - u;
+  v %= p1; if (v < 0) v += p1; if (v > n1) v = p1 - v;
+  return g[u * (n1 + 1) + v];
+}
+
+// Forward FFT along x of the real windows K(m_i, m_j) = G(bi + d(m_i),
+// bj + d(m_j)), d(m) = m below ceil(L/2) and m - L above (the offsets a
+// linear convolution of a box with itself needs).
+__global__ __launch_bounds__(kFftThreads) void k_spec_rows(const double* __restrict__ g, int n2,
+                                                           int n1, const int4* __restrict__ keys,
+                                                           int Li, int Lj, FftDesc fj,
+                                                           const cplx<double>* __restrict__ twj,
+                                                           cplx<double>* __restrict__ out, int ppw) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
+  const int slot = blockIdx.y;
+  const int4 key = keys[slot];
+  const int Lh = Lj / 2 + 1;
+  const int hi_i = (Li + 1) / 2, hi_j = (Lj + 1) / 2;
+  const int q0 = blockIdx.x * ppw;
+  for (int e = threadIdx.x; e < ppw * Lj; e += kFftThreads) {
+    const int qq = e / Lj, c = e - qq * Lj;
+    const int ra = 2 * (q0 + qq), rb = ra + 1;
+    const long long dj = c < hi_j ? c : c - Lj;
+    double va = 0.0, vb = 0.0;
+    if (ra < Li) va = g_lookup(g, n2, n1, key.x + (ra < hi_i ? ra : ra - Li), key.y + dj);
+    if (rb < Li) vb = g_lookup(g, n2, n1, key.x + (rb < hi_i ? rb : rb - Li), key.y + dj);
+    buf[qq * Lj + c] = cplx<double>{va, vb};
+  }
+  __syncthreads();
+  fft_lds<double>(buf, fj, Lj, ppw, twj, false);
+  for (int e = threadIdx.x; e < ppw * Lh; e += kFftThreads) {
+    const int qq = e / Lh, k = e - qq * Lh;
+    const int ra = 2 * (q0 + qq), rb = ra + 1;
+    const cplx<double> z = buf[qq * Lj + k];
+    const cplx<double> zn = buf[qq * Lj + (k == 0 ? 0 : Lj - k)];
+    const size_t base = static_cast<size_t>(slot) * Li * Lh;
+    if (ra < Li) out[base + static_cast<size_t>(ra) * Lh + k] = cplx<double>{0.5 * (z.x + zn.x), 0.5 * (z.y - zn.y)};
+    if (rb < Li) out[base + static_cast<size_t>(rb) * Lh + k] = cplx<double>{0.5 * (z.y + zn.y), 0.5 * (zn.x - z.x)};
+  }
+}
+
+// Forward FFT along y, then the flip phases and the 1/(Li Lj) normalisation
+// of the inverse transforms are folded in; output in T.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_spec_cols(const cplx<double>* __restrict__ in,
+                                                           const int4* __restrict__ keys, int Li,
+                                                           int Lj, FftDesc fi,
+                                                           const cplx<double>* __restrict__ twi,
+                                                           const cplx<double>* __restrict__ twj,
+                                                           cplx<T>* __restrict__ out, int cpw) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
+  const int slot = blockIdx.y;
+  const int4 key = keys[slot];
+  const int Lh = Lj / 2 + 1;
+  const int cs = Li + 1;
+  const int k0 = blockIdx.x * cpw;
+  const size_t base = static_cast<size_t>(slot) * Li * Lh;
+  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
+    const int r = e / cpw, c = e - r * cpw;
+    const int k = k0 + c;
+    buf[c * cs + r] = (k < Lh) ? in[base + static_cast<size_t>(r) * Lh + k] : cplx<double>{0.0, 0.0};
+  }
+  __syncthreads();
+  fft_lds<double>(buf, fi, cs, cpw, twi, false);
+  const double scale = 1.0 / (double(Li) * double(Lj));
+  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
+    const int r = e / cpw, c = e - r * cpw;
+    const int k = k0 + c;
+    if (k >= Lh) continue;
+    cplx<double> v = buf[c * cs + r];
+    v.x *= scale;
+    v.y *= scale;
+    if (key.z >= 0) v = cmul(v, twi[(static_cast<long long>(r) * key.z) % Li]);
+    if (key.w >= 0) v = cmul(v, twj[(static_cast<long long>(k) * key.w) % Lj]);
+    out[base + static_cast<size_t>(r) * Lh + k] = cplx<T>{T(v.x), T(v.y)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Apply kernels
+// ---------------------------------------------------------------------------
+
+// div of a 2-plane frame field at local (r, q) of box b, with the boundary
+// rules of D^-_x, D^-_y on the whole grid and zeros outside the frame's
+// support.
+template <typename T>
+__device__ __forceinline__ T div_at(const T* __restrict__ u, const Frame& f, int b, int gi, int gj,
+                                    int r, int q, int n2, int n1, T inv_h) {
+  const T* u1 = u + b * f.box_stride;
+  const T* u2 = u1 + f.plane_stride;
+  const long long o = static_cast<long long>(r) * f.pitch + q;
+  const T a = (gj == n1 - 1) ? T(0) : u1[o];
+  const T am = (q > 0) ? u1[o - 1] : T(0);
+  const T c = (gi == n2 - 1) ? T(0) : u2[o];
+  const T cm = (r > 0) ? u2[o - f.pitch] : T(0);
+  return ((a - am) + (c - cm)) * inv_h;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
+                                                                Frame uf) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int b = blockIdx.y;
+  const GreenBox bx = d.boxes[b];
+  const int Lj = d.Lj, Lh = d.Lh;
+  const int q0 = blockIdx.x * d.ppw;
+  if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
+  for (int e = threadIdx.x; e < d.ppw * Lj; e += kFftThreads) {
+    const int qq = e / Lj, c = e - qq * Lj;
+    const int ra = 2 * (q0 + qq), rb = ra + 1;
+    T va = T(0), vb = T(0);
+    if (c < bx.nj) {
+      if (ra < bx.ni) va = div_at(u, uf, b, bx.i0 + ra, bx.j0 + c, ra, c, d.n2, d.n1, d.inv_h);
+      if (rb < bx.ni) vb = div_at(u, uf, b, bx.i0 + rb, bx.j0 + c, rb, c, d.n2, d.n1, d.inv_h);
+    }
+    buf[qq * Lj + c] = C{va, vb};
+  }
+  __syncthreads();
+  fft_lds<T>(buf, d.fj, Lj, d.ppw, d.tw_j, false);
+  C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
+  for (int e = threadIdx.x; e < d.ppw * Lh; e += kFftThreads) {
+    const int qq = e / Lh, k = e - qq * Lh;
+    const int ra = 2 * (q0 + qq), rb = ra + 1;
+    const C z = buf[qq * Lj + k];
+    const C zn = buf[qq * Lj + (k == 0 ? 0 : Lj - k)];
+    if (ra < bx.ni) S[static_cast<size_t>(ra) * Lh + k] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
+    if (rb < bx.ni) S[static_cast<size_t>(rb) * Lh + k] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_green_cols(GreenDev<T> d) {
+  using C = cplx<T>;
+  constexpr int E = FftCap<T>::elems;
+  extern __shared__ unsigned char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int b = blockIdx.y;
+  const GreenBox bx = d.boxes[b];
+  const int Li = d.Li, Lh = d.Lh, cpw = d.cpw;
+  const int cs = Li + 1;
+  const int k0 = blockIdx.x * cpw;
+  C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
+  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
+    const int r = e / cpw, c = e - r * cpw;
+    const int k = k0 + c;
+    buf[c * cs + r] = (r < bx.ni && k < Lh) ? S[static_cast<size_t>(r) * Lh + k] : C{T(0), T(0)};
+  }
+  __syncthreads();
+  fft_lds<T>(buf, d.fi, cs, cpw, d.tw_i, false);
+  // Phi = X K00 + conj(X(-ki)) K01 + X(-ki) K10 + conj(X) K11
+  const C* s00 = d.spec + static_cast<size_t>(bx.k00) * Li * Lh;
+  const C* s01 = d.spec + static_cast<size_t>(bx.k01) * Li * Lh;
+  const C* s10 = d.spec + static_cast<size_t>(bx.k10) * Li * Lh;
+  const C* s11 = d.spec + static_cast<size_t>(bx.k11) * Li * Lh;
+  C res[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int e = threadIdx.x + s * kFftThreads;
+    if (e < cpw * Li) {
+      const int ki = e / cpw, c = e - ki * cpw;
+      const int k = k0 + c;
+      C x = buf[c * cs + ki];
+      C xn = buf[c * cs + (ki == 0 ? 0 : Li - ki)];
+      C acc{T(0), T(0)};
+      if (k < Lh) {
+        const size_t o = static_cast<size_t>(ki) * Lh + k;
+        acc = cmul(x, s00[o]);
+        acc = cadd(acc, cmul(cconj(xn), s01[o]));
+        acc = cadd(acc, cmul(xn, s10[o]));
+        acc = cadd(acc, cmul(cconj(x), s11[o]));
+      }
+      res[s] = acc;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int e = threadIdx.x + s * kFftThreads;
+    if (e < cpw * Li) {
+      const int ki = e / cpw, c = e - ki * cpw;
+      buf[c * cs + ki] = res[s];
+    }
+  }
+  __syncthreads();
+  fft_lds<T>(buf, d.fi, cs, cpw, d.tw_i, true);
+  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
+    const int r = e / cpw, c = e - r * cpw;
+    const int k = k0 + c;
+    if (r < bx.ni && k < Lh) S[static_cast<size_t>(r) * Lh + k] = buf[c * cs + r];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_green_rows_inv(GreenDev<T> d, T* __restrict__ phi,
+                                                                Frame pf) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const int b = blockIdx.y;
+  const GreenBox bx = d.boxes[b];
+  const int Lj = d.Lj, Lh = d.Lh;
+  const int q0 = blockIdx.x * d.ppw;
+  if (2 * q0 >= bx.ni) return;
+  const C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
+  const int half = Lj / 2;
+  for (int e = threadIdx.x; e < d.ppw * Lj; e += kFftThreads) {
+    const int qq = e / Lj, k = e - qq * Lj;
+    const int ra = 2 * (q0 + qq), rb = ra + 1;
+    const int kk = k <= half ? k : Lj - k;
+    const C a = ra < bx.ni ? S[static_cast<size_t>(ra) * Lh + kk] : C{T(0), T(0)};
+    const C c = rb < bx.ni ? S[static_cast<size_t>(rb) * Lh + kk] : C{T(0), T(0)};
+    buf[qq * Lj + k] = k <= half ? C{a.x - c.y, a.y + c.x} : C{a.x + c.y, c.x - a.y};
+  }
+  __syncthreads();
+  fft_lds<T>(buf, d.fj, Lj, d.ppw, d.tw_j, true);
+  T* out = phi + b * pf.box_stride;
+  for (int e = threadIdx.x; e < d.ppw * bx.nj; e += kFftThreads) {
+    const int qq = e / bx.nj, c = e - qq * bx.nj;
+    const int ra = 2 * (q0 + qq), rb = ra + 1;
+    const C z = buf[qq * Lj + c];
+    if (ra < bx.ni) out[static_cast<long long>(ra) * pf.pitch + c] = z.x;
+    if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+template <typename F>
+static void allow_lds(F* f, size_t bytes) {
+  if (bytes > 65536) TVS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(bytes)));
+}
+
+static int pick_batch(int n, int cap_elems, size_t elem_bytes, int max_batch, size_t max_lds,
+                      int stride_pad) {
+  int b = std::min(max_batch, std::max(1, (kFftThreads * cap_elems) / n));
+  while (b > 1 && size_t(b) * (n + stride_pad) * elem_bytes > max_lds) --b;
+  if (size_t(n) * b > size_t(kFftThreads) * cap_elems)
+    throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
+  if (size_t(b) * (n + stride_pad) * elem_bytes > 160 * 1024)
+    throw Error(-1, "FFT length " + std::to_string(n) + " does not fit in LDS");
+  return b;
+}
+
+template <typename T>
+GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<int, 4>>& boxes,
+                        hipStream_t s)
+    : n2(table.n2), n1(table.n1), nbox(int(boxes.size())) {
+  rows_max = cols_max = 0;
+  for (auto& bx : boxes) {
+    rows_max = std::max(rows_max, bx[2]);
+    cols_max = std::max(cols_max, bx[3]);
+  }
+  Li = smooth_even_at_least(2 * rows_max - 1);
+  Lj = smooth_even_at_least(2 * cols_max - 1);
+  const int Lh = Lj / 2 + 1;
+  const FftDesc fi = make_fft_desc(Li), fj = make_fft_desc(Lj);
+
+  // slots, deduplicated by window base and flip phase
+  std::map<SlotKey, int> slots;
+  std::vector<int4> keys;
+  auto slot_of = [&](SlotKey k) {
+    auto it = slots.find(k);
+    if (it != slots.end()) return it->second;
+    const int id = int(keys.size());
+    slots[k] = id;
+    keys.push_back(make_int4(k.bi, k.bj, k.pi, k.pj));
+    return id;
+  };
+  std::vector<GreenBox> hb(nbox);
+  for (int b = 0; b < nbox; ++b) {
+    const int i0 = boxes[b][0], j0 = boxes[b][1], ni = boxes[b][2], nj = boxes[b][3];
+    if (i0 < 0 || j0 < 0 || ni < 1 || nj < 1 || i0 + ni > n2 || j0 + nj > n1)
+      throw Error(-1, "Green box outside the grid");
+    GreenBox g{i0, j0, ni, nj, 0, 0, 0, 0};
+    g.k00 = slot_of({0, 0, -1, -1});
+    g.k01 = slot_of({0, 2 * j0 + nj, -1, nj - 1});
+    g.k10 = slot_of({2 * i0 + ni, 0, ni - 1, -1});
+    g.k11 = slot_of({2 * i0 + ni, 2 * j0 + nj, ni - 1, nj - 1});
+    hb[b] = g;
+  }
+  nslot = keys.size();
+
+  boxes_d_.alloc(sizeof(GreenBox) * nbox);
+  TVS_HIP(hipMemcpyAsync(boxes_d_.p, hb.data(), sizeof(GreenBox) * nbox, hipMemcpyHostToDevice, s));
+  tw_i_ = make_twiddles<T>(Li, s);
+  tw_j_ = make_twiddles<T>(Lj, s);
+  spec_.alloc(sizeof(cplx<T>) * nslot * size_t(Li) * Lh);
+  S_.alloc(sizeof(cplx<T>) * size_t(nbox) * rows_max * Lh);
+
+  // build the window spectra in float64, a chunk of slots at a time
+  {
+    DevBuf tw_i64 = make_twiddles<double>(Li, s), tw_j64 = make_twiddles<double>(Lj, s);
+    DevBuf keys_d(sizeof(int4) * nslot);
+    TVS_HIP(hipMemcpyAsync(keys_d.p, keys.data(), sizeof(int4) * nslot, hipMemcpyHostToDevice, s));
+    const size_t per_slot = size_t(Li) * Lh;
+    const size_t chunk = std::max<size_t>(1, (size_t(512) << 20) / (per_slot * sizeof(cplx<double>)));
+    DevBuf tmp(sizeof(cplx<double>) * std::min(chunk, nslot) * per_slot);
+    const int ppw = pick_batch(Lj, FftCap<double>::elems, sizeof(cplx<double>), 8, 96 * 1024, 0);
+    const int cpw = pick_batch(Li, FftCap<double>::elems, sizeof(cplx<double>), 16, 128 * 1024, 1);
+    const size_t lds_r = size_t(ppw) * Lj * sizeof(cplx<double>);
+    const size_t lds_c = size_t(cpw) * (Li + 1) * sizeof(cplx<double>);
+    allow_lds(k_spec_rows, lds_r);
+    allow_lds(k_spec_cols<T>, lds_c);
+    for (size_t s0 = 0; s0 < nslot; s0 += chunk) {
+      const int ns = int(std::min(chunk, nslot - s0));
+      hipLaunchKernelGGL(k_spec_rows, dim3((Li / 2 + ppw - 1) / ppw, ns), dim3(kFftThreads), lds_r, s,
+                         table.g.as<double>(), n2, n1, keys_d.as<int4>() + s0, Li, Lj, fj,
+                         tw_j64.as<cplx<double>>(), tmp.as<cplx<double>>(), ppw);
+      TVS_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_spec_cols<T>, dim3((Lh + cpw - 1) / cpw, ns), dim3(kFftThreads), lds_c, s,
+                         tmp.as<cplx<double>>(), keys_d.as<int4>() + s0, Li, Lj, fi,
+                         tw_i64.as<cplx<double>>(), tw_j64.as<cplx<double>>(),
+                         spec_.as<cplx<T>>() + s0 * per_slot, cpw);
+      TVS_LAUNCH_CHECK();
+    }
+    TVS_HIP(hipStreamSynchronize(s));
+  }
+
+  dev_.n2 = n2;
+  dev_.n1 = n1;
+  dev_.Li = Li;
+  dev_.Lj = Lj;
+  dev_.Lh = Lh;
+  dev_.rows_max = rows_max;
+  dev_.ppw = pick_batch(Lj, FftCap<T>::elems, sizeof(cplx<T>), 8, 96 * 1024, 0);
+  dev_.cpw = pick_batch(Li, FftCap<T>::elems, sizeof(cplx<T>), 16, 128 * 1024, 1);
+  dev_.inv_h = T(1) / T(table.h);
+  dev_.boxes = boxes_d_.as<GreenBox>();
+  dev_.tw_i = tw_i_.as<cplx<T>>();
+  dev_.tw_j = tw_j_.as<cplx<T>>();
+  dev_.S = S_.as<cplx<T>>();
+  dev_.spec = spec_.as<cplx<T>>();
+  dev_.fi = fi;
+  dev_.fj = fj;
+  allow_lds(k_green_rows_fwd<T>, size_t(dev_.ppw) * Lj * sizeof(cplx<T>));
+  allow_lds(k_green_rows_inv<T>, size_t(dev_.ppw) * Lj * sizeof(cplx<T>));
+  allow_lds(k_green_cols<T>, size_t(dev_.cpw) * (Li + 1) * sizeof(cplx<T>));
+}
+
+template <typename T>
+size_t GreenPlan<T>::bytes() const {
+  return spec_.bytes + S_.bytes + boxes_d_.bytes + tw_i_.bytes + tw_j_.bytes;
+}
+
+template <typename T>
+void GreenPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t s) {
+  const size_t lds_r = size_t(dev_.ppw) * Lj * sizeof(cplx<T>);
+  const size_t lds_c = size_t(dev_.cpw) * (Li + 1) * sizeof(cplx<T>);
+  const int row_groups = ((rows_max + 1) / 2 + dev_.ppw - 1) / dev_.ppw;
+  hipLaunchKernelGGL(k_green_rows_fwd<T>, dim3(row_groups, nbox), dim3(kFftThreads), lds_r, s, dev_, u, uf);
+  TVS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_green_cols<T>, dim3((dev_.Lh + dev_.cpw - 1) / dev_.cpw, nbox), dim3(kFftThreads),
+                     lds_c, s, dev_);
+  TVS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_green_rows_inv<T>, dim3(row_groups, nbox), dim3(kFftThreads), lds_r, s, dev_, phi, pf);
+  TVS_LAUNCH_CHECK();
+}
+
+template class GreenPlan<float>;
+template class GreenPlan<double>;
+
+}  // namespace tvs

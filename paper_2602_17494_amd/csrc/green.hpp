@@ -1,0 +1,90 @@
+// Moore-Penrose inverse of the Neumann Laplacian of a rectangular grid,
+// applied to data supported on boxes and read back on the same boxes.
+//
+// The paper evaluates (Delta)^dagger through the 2-D DCT (eqs.
+// form:DiscInvLapl, form:DiscInvLaplTild), and for data supported on a block
+// it keeps the full frequency sum in its block formula (eq.
+// invLaplLowCapLong).  Here the same operator is realised exactly through
+// the image identity: the 5-point Neumann Laplacian of an n2 x n1 grid is
+// the periodic Laplacian of the 2n2 x 2n1 torus acting on the half-sample
+// even extension, so (Delta)^dagger b at x equals
+//     sum_y b(y) [G(x-y) + G(x - R_x y) + G(x - R_y y) + G(x - R_x R_y y)]
+// with G the pseudo-inverse kernel of the torus and R_x, R_y the two
+// reflections.  For a source box B read on the same box, each of the four
+// terms is a linear convolution of the (possibly flipped) box data with a
+// window of G; all four are evaluated with one forward and one inverse FFT of
+// a smooth length L >= 2 |B| - 1 per axis, combining the four precomputed
+// window spectra in the frequency domain.  G itself is tabulated once per
+// grid in float64 by two dense contractions (a cosine sum over the torus
+// spectrum).
+#pragma once
+
+#include <array>
+#include <map>
+#include <memory>
+
+#include "fft_lds.hpp"
+
+namespace tvs {
+
+// Source = window box of the Green operator, and the four spectrum slots
+// (direct, x-reflected, y-reflected, both) used by it.
+struct GreenBox {
+  int i0, j0, ni, nj;
+  int k00, k01, k10, k11;
+};
+
+// Layout of a field stored as one frame per box (or one global frame):
+// element (plane c, local row r, local column q) of box b is at
+// base[b * box_stride + c * plane_stride + r * pitch + q].
+struct Frame {
+  long long box_stride;
+  long long plane_stride;
+  int pitch;
+};
+
+// Tabulated torus kernel G(u, v), u in [0, n2], v in [0, n1], float64.
+struct GreenTable {
+  int n2, n1;
+  double h;
+  DevBuf g;  // (n2 + 1) * (n1 + 1) doubles
+  GreenTable(int n2, int n1, double h, hipStream_t s);
+};
+
+template <typename T>
+struct GreenDev {
+  int n2, n1;
+  int Li, Lj, Lh;
+  int rows_max;
+  int ppw, cpw;
+  T inv_h;
+  const GreenBox* boxes;
+  const cplx<T>* tw_i;
+  const cplx<T>* tw_j;
+  cplx<T>* S;
+  const cplx<T>* spec;
+  FftDesc fi, fj;
+};
+
+template <typename T>
+class GreenPlan {
+ public:
+  // Boxes are (i0, j0, ni, nj) on the n2 x n1 grid of `table`.
+  GreenPlan(const GreenTable& table, const std::vector<std::array<int, 4>>& boxes,
+            hipStream_t stream);
+  // phi = R_B (Delta)^dagger E_B div(u) on every box B, where u is a 2-plane
+  // field (x- and y-component) stored in frame `uf` with zeros outside its
+  // support, and div uses the grid's boundary rules (Section 4.1).
+  void apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t stream);
+
+  int n2, n1, nbox, Li, Lj;
+  int rows_max, cols_max;
+  size_t nslot = 0;
+  size_t bytes() const;
+
+ private:
+  GreenDev<T> dev_{};
+  DevBuf boxes_d_, tw_i_, tw_j_, spec_, S_;
+};
+
+}  // namespace tvs

@@ -1,0 +1,136 @@
+// Internal definitions shared by the HIP translation units of libtvs.
+//
+// Grids: an image grid Omega has N2 rows (y, index i) and N1 columns (x,
+// index j); the Step-1 grid Omega-tilde has (N2+1) x (N1+1) points and holds
+// Omega as its first N2 rows and N1 columns (Section 4.1).  All device arrays
+// are row-major and planar: plane-major, then row, then column.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace tvs {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define TVS_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      throw ::tvs::Error(-3, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TVS_LAUNCH_CHECK()                                                     \
+  do {                                                                         \
+    hipError_t e_ = hipGetLastError();                                         \
+    if (e_ != hipSuccess)                                                      \
+      throw ::tvs::Error(-3, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on float2 / double2
+// ---------------------------------------------------------------------------
+template <typename T> struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+template <typename T> using cplx = cx<T>;
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C>
+__device__ __forceinline__ C cconj(C a) { return C{a.x, -a.y}; }
+
+// ---------------------------------------------------------------------------
+// device buffer (RAII, owned by the library)
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error(-2, "device allocation of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename U> U* as() const { return static_cast<U*>(p); }
+};
+template <typename U> U* dptr(const DevBuf& b) { return static_cast<U*>(b.p); }
+
+// ---------------------------------------------------------------------------
+// one axis of a subdomain layout (Section 6.1)
+// ---------------------------------------------------------------------------
+constexpr int kMaxSub = 32;  // subdomains per axis
+
+struct AxisLayout {
+  int n;        // points on the Omega-tilde axis
+  int m;        // subdomains on this axis
+  int s;        // width of the stripe shared by two neighbours
+  int cut[kMaxSub + 1];
+  int start[kMaxSub];
+  int end[kMaxSub];
+};
+
+// One-dimensional partition-of-unity weight (linear ramps across each shared
+// stripe, 1 on the rest of the core, 0 outside the subdomain).
+template <typename T>
+__host__ __device__ __forceinline__ T axis_theta(const AxisLayout& a, int m, int x) {
+  if (x < a.start[m] || x >= a.end[m]) return T(0);
+  const int lo = a.s / 2, hi = a.s - a.s / 2;
+  if (m > 0 && x < a.cut[m] + hi) return (T(x - (a.cut[m] - lo)) + T(0.5)) / T(a.s);
+  if (m < a.m - 1 && x >= a.cut[m + 1] - lo)
+    return T(1) - (T(x - (a.cut[m + 1] - lo)) + T(0.5)) / T(a.s);
+  return T(1);
+}
+
+// ---------------------------------------------------------------------------
+// FFT plan data passed to kernels by value
+// ---------------------------------------------------------------------------
+constexpr int kMaxPass = 24;
+
+struct FftDesc {
+  int n;
+  int npass;
+  int radix[kMaxPass];
+};
+
+// smallest even integer >= n whose only prime factors are 2, 3 and 5
+int smooth_even_at_least(int n);
+FftDesc make_fft_desc(int n);
+
+}  // namespace tvs

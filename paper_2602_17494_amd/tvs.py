@@ -1,0 +1,200 @@
+"""Thin ctypes binding of libtvs (include/tvs.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Arrays are torch tensors on the GPU (float32 or float64,
+contiguous); PyTorch provides device memory and streams.  If the library is
+not built this module raises on import of the library, never falling back to
+any other implementation.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtvs.so")
+
+TVS_F32, TVS_F64 = 0, 1
+TVS_IRV2, TVS_IRV1 = 0, 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("alpha", ctypes.c_double), ("t", ctypes.c_double),
+                ("h", ctypes.c_double), ("eps", ctypes.c_double), ("variant", ctypes.c_int)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("M2", ctypes.c_int), ("M1", ctypes.c_int), ("s_y", ctypes.c_int),
+                ("s_x", ctypes.c_int), ("alpha_hat", ctypes.c_double)]
+
+
+class Iters(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int), ("inner", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("sweeps_done", ctypes.c_int), ("energy", ctypes.c_double),
+                ("gap", ctypes.c_double), ("residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TvsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libtvs error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libtvs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.tvs_ctx_create.argtypes = [ci, ctypes.POINTER(vp)]
+    lib.tvs_ctx_create.restype = ci
+    lib.tvs_ctx_destroy.argtypes = [vp]
+    lib.tvs_ctx_destroy.restype = None
+    lib.tvs_last_error.argtypes = []
+    lib.tvs_last_error.restype = ctypes.c_char_p
+    lib.tvs_ctx_bytes.argtypes = [vp]
+    lib.tvs_ctx_bytes.restype = ctypes.c_size_t
+    P, L, I, S = (ctypes.POINTER(Params), ctypes.POINTER(Layout), ctypes.POINTER(Iters),
+                  ctypes.POINTER(Stats))
+    lib.tvs_step1.argtypes = [vp, vp, ci, ci, ci, P, L, I, vp, S, vp]
+    lib.tvs_step1.restype = ci
+    lib.tvs_step2.argtypes = [vp, vp, vp, ci, ci, ci, P, L, I, vp, S, vp]
+    lib.tvs_step2.restype = ci
+    lib.tvs_schwarz_solve.argtypes = [vp, vp, ci, ci, ci, P, L, I, vp, vp, S, vp]
+    lib.tvs_schwarz_solve.restype = ci
+    lib.tvs_project_div_free.argtypes = [vp, vp, ci, ci, ci, cd, vp, vp]
+    lib.tvs_project_div_free.restype = ci
+    _lib = lib
+    return lib
+
+
+EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_bytes", "tvs_step1",
+            "tvs_step2", "tvs_schwarz_solve", "tvs_project_div_free"]
+
+
+def _check(code):
+    if code != 0:
+        raise TvsError(code, load().tvs_last_error().decode())
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return TVS_F32
+    if t.dtype == torch.float64:
+        return TVS_F64
+    raise TypeError("tensors must be float32 or float64")
+
+
+def _dev(t, shape, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("all tensors must share one dtype")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_params(delta, alpha, t=0.125, h=1.0, eps=1e-3, variant=TVS_IRV2):
+    return Params(float(delta), float(alpha), float(t), float(h), float(eps), int(variant))
+
+
+def make_layout(m2=1, m1=1, s_y=0, s_x=0, alpha_hat=0.0):
+    return Layout(int(m2), int(m1), int(s_y), int(s_x), float(alpha_hat))
+
+
+def make_iters(sweeps, inner, tol=0.0):
+    return Iters(int(sweeps), int(inner), float(tol))
+
+
+class Context:
+    """A libtvs context on one GPU (caches plans and work buffers)."""
+
+    def __init__(self, device=0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.tvs_ctx_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", int(device))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().tvs_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def bytes(self):
+        return int(load().tvs_ctx_bytes(self._h))
+
+    def step1(self, d0, params, layout, iters, tau_out=None, stats=True):
+        n2, n1 = d0.shape
+        if tau_out is None:
+            tau_out = torch.empty((2, n2 + 1, n1 + 1), dtype=d0.dtype, device=d0.device)
+        st = Stats()
+        _check(load().tvs_step1(self._h, _dev(d0, (n2, n1)), n2, n1, _dtype_code(d0),
+                                ctypes.byref(params), ctypes.byref(layout), ctypes.byref(iters),
+                                _dev(tau_out, (2, n2 + 1, n1 + 1), d0.dtype),
+                                ctypes.byref(st) if stats else None, _stream(d0.device)))
+        return tau_out, (st.as_dict() if stats else None)
+
+    def step2(self, d0, tau, params, layout, iters, d_out=None, stats=True):
+        n2, n1 = d0.shape
+        if d_out is None:
+            d_out = torch.empty_like(d0)
+        st = Stats()
+        _check(load().tvs_step2(self._h, _dev(d0, (n2, n1)), _dev(tau, (2, n2 + 1, n1 + 1), d0.dtype),
+                                n2, n1, _dtype_code(d0), ctypes.byref(params), ctypes.byref(layout),
+                                ctypes.byref(iters), _dev(d_out, (n2, n1), d0.dtype),
+                                ctypes.byref(st) if stats else None, _stream(d0.device)))
+        return d_out, (st.as_dict() if stats else None)
+
+    def schwarz_solve(self, d0, params, layout, iters, d_out=None, tau_out=None, stats=True):
+        n2, n1 = d0.shape
+        if d_out is None:
+            d_out = torch.empty_like(d0)
+        st = (Stats * 2)()
+        tau_p = None if tau_out is None else _dev(tau_out, (2, n2 + 1, n1 + 1), d0.dtype)
+        _check(load().tvs_schwarz_solve(self._h, _dev(d0, (n2, n1)), n2, n1, _dtype_code(d0),
+                                        ctypes.byref(params), ctypes.byref(layout),
+                                        ctypes.byref(iters), _dev(d_out, (n2, n1), d0.dtype),
+                                        tau_p, st if stats else None, _stream(d0.device)))
+        return d_out, ([st[0].as_dict(), st[1].as_dict()] if stats else None)
+
+    def project_div_free(self, u, h=1.0, out=None):
+        _, n2, n1 = u.shape
+        if out is None:
+            out = torch.empty_like(u)
+        _check(load().tvs_project_div_free(self._h, _dev(u, (2, n2, n1)), n2, n1, _dtype_code(u),
+                                           float(h), _dev(out, (2, n2, n1), u.dtype),
+                                           _stream(u.device)))
+        return out
