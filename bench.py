@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the TV-Stokes hot path on one MI355X.
+
+One step = one full solve of the workload: Step 1 (TFS dual iterations with
+the divergence-free projection) and Step 2 (IRV2 dual iterations), each as
+`sweeps` outer iterations of the overlapping Schwarz method with `inner`
+subdomain iterations, on a 2048 x 2048 float32 image (sigma = 0.1) split
+into 8 x 8 subdomains with a 16-pixel shared stripe; FP64 only in the energy,
+residual and duality-gap reductions.  The input image is resident in device
+memory before the timed region starts.
+
+value = pixel-iterations per second / 1e6, counting each global grid point
+once per dual iteration: (|Omega-tilde| + |Omega|) * sweeps * inner per step.
+
+Also reported: p50/p99 latency of one solve, the roofline of the dominant
+kernel (achieved algorithmic GB/s from HIP events around its launches), the
+same solve in float64 (error of the float32 image against it) and the plain
+single-domain float64 solve with the same number of dual iterations per step,
+and the FP64 CPU oracle timed on a bounded sample of the workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--sigma", type=float, default=0.1)
+    ap.add_argument("--layout", type=int, nargs=4, default=[8, 8, 16, 16], metavar=("M2", "M1", "SY", "SX"))
+    ap.add_argument("--sweeps", type=int, default=20)
+    ap.add_argument("--inner", type=int, default=500)
+    ap.add_argument("--no-compare", action="store_true", help="skip the float64 comparator solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2602_17494_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it is missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(kernel)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(n, sigma, lay):
+    """Time the FP64 oracle on a bounded sample of the workload: one
+    subdomain's inner loop of each step (Algorithm 5 for Step 1, Algorithm 3
+    for Step 2) at 1 and at 2 (Step 2: 1 and 3) inner iterations, which
+    separates its per-sweep set-up from its per-iteration cost, and scale to
+    the full workload's sweeps x inner x subdomains."""
+    import numpy as np
+
+    import synth
+    from oracle import schwarz as osw
+    from oracle import solvers as osv
+
+    _, d64 = synth.noisy_f32(n, n, sigma, 31)
+    delta, alpha = synth.params_for_sigma(sigma)
+    m2, m1, sy, sx = lay
+    l1 = osw.Layout(n, n, m2, m1, sy, sx, step=1)
+    l2 = osw.Layout(n, n, m2, m1, sy, sx, step=2)
+    f1 = osv.tfs_data(d64, delta)
+    p1 = np.zeros((2, 2) + l1.shape)
+    m = l1.count // 2 + m1 // 2  # an interior subdomain
+    t = []
+    for iters in (1, 2):
+        t0 = time.perf_counter()
+        osw.inner_tfs_local(l1, m, p1, np.zeros_like(p1), f1, iters, 0.125)
+        t.append(time.perf_counter() - t0)
+    s1_iter = max(t[1] - t[0], 1e-9)
+    s1_sweep = max(t[0] - s1_iter, 0.0)
+    f2 = alpha * d64
+    p2 = np.zeros((1, 2) + l2.shape)
+    t2 = []
+    for iters in (1, 3):
+        t0 = time.perf_counter()
+        osw.inner_rof(l2, m, p2, np.zeros_like(p2), f2, iters, 0.125)
+        t2.append(time.perf_counter() - t0)
+    s2_iter = max((t2[1] - t2[0]) / 2, 1e-9)
+    s2_sweep = max(t2[0] - s2_iter, 0.0)
+    return s1_iter, s1_sweep, s2_iter, s2_sweep, l1.count, sum(t) + sum(t2)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design note only", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2602_17494_amd import Context, make_iters, make_layout, make_params
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    n = args.size
+    delta, alpha = synth.params_for_sigma(args.sigma)
+    _, d64 = synth.noisy_f32(n, n, args.sigma, 31)
+    ctx = Context(0)
+    dev = torch.device("cuda", 0)
+    d0 = torch.tensor(d64, dtype=torch.float32, device=dev)
+    tau = torch.empty((2, n + 1, n + 1), dtype=torch.float32, device=dev)
+    d = torch.empty_like(d0)
+    prm = make_params(delta, alpha)
+    lay = make_layout(*args.layout)
+    its = make_iters(args.sweeps, args.inner)
+    pix_iters = ((n + 1) * (n + 1) + n * n) * args.sweeps * args.inner
+
+    for _ in range(args.warmup):
+        ctx.schwarz_solve(d0, prm, lay, its, d_out=d, tau_out=tau)
+    torch.cuda.synchronize()
+    ctx.timing_reset()
+    ctx.timing(True)
+    lat = []
+    stats = None
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        _, stats = ctx.schwarz_solve(d0, prm, lay, its, d_out=d, tau_out=tau)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    ctx.timing(False)
+    timing = ctx.timing_read()
+    value = pix_iters * args.steps / total / 1e6
+
+    # dominant kernel class: largest total time
+    dom = max(timing.items(), key=lambda kv: kv[1][1])
+    dname, (dlaunch, dms, dbytes) = dom
+    achieved = (dbytes / dlaunch) / (dms / dlaunch * 1e-3) / 1e9
+    traffic = read_traffic(dname)
+    breakdown = {k: {"launches": v[0], "ms": round(v[1], 3),
+                     "gbs": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+                 for k, v in sorted(timing.items(), key=lambda kv: -kv[1][1])}
+
+    out = {
+        "metric": "Mpix*iter/s at 2048^2 (FP32 Schwarz, both TV-Stokes steps)",
+        "value": round(value, 1),
+        "unit": "Mpix*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{n}x{n} float32 image (seeded piecewise-smooth + Gaussian noise "
+                         f"sigma={args.sigma}), TFS + IRV2, {args.layout[0]}x{args.layout[1]} "
+                         f"subdomains, shared stripe {args.layout[2]}x{args.layout[3]} px, "
+                         f"{args.sweeps} sweeps x {args.inner} inner iterations per step, "
+                         "FP64 energy/residual/gap reductions"),
+            "delta": delta, "alpha": alpha, "t": 0.125,
+        },
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4),
+                      "p99": round(float(np.percentile(lat, 99)), 4)},
+        "per_step": {
+            "step1_seconds": round(stats[0]["seconds"], 4),
+            "step2_seconds": round(stats[1]["seconds"], 4),
+            "step1_mpix_iter_s": round((n + 1) ** 2 * args.sweeps * args.inner / stats[0]["seconds"] / 1e6, 1),
+            "step2_mpix_iter_s": round(n * n * args.sweeps * args.inner / stats[1]["seconds"] / 1e6, 1),
+            "energy": [stats[0]["energy"], stats[1]["energy"]],
+            "gap": [stats[0]["gap"], stats[1]["gap"]],
+            "residual": [stats[0]["residual"], stats[1]["residual"]],
+        },
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": dbytes / dlaunch,
+                     "avg_launch_us": round(dms / dlaunch * 1e3, 2)},
+        "kernels": breakdown,
+    }
+
+    if not args.no_compare:
+        d_f32 = d.double().cpu()
+        d064 = torch.tensor(d64, dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        d_f64, _ = ctx.schwarz_solve(d064, prm, lay, its)
+        torch.cuda.synchronize()
+        t_f64 = time.perf_counter() - t0
+        err = float((d_f32 - d_f64.cpu()).abs().max())
+        t0 = time.perf_counter()
+        d_plain, st_plain = ctx.schwarz_solve(d064, prm, make_layout(1, 1, 0, 0), its)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        out["compare"] = {
+            "f64_same_layout": {"seconds": round(t_f64, 3),
+                                "mpix_iter_s": round(pix_iters / t_f64 / 1e6, 1),
+                                "max_abs_err_f32_image": err},
+            "f64_plain_single_domain": {"seconds": round(t_plain, 3),
+                                        "mpix_iter_s": round(pix_iters / t_plain / 1e6, 1),
+                                        "step1_seconds": round(st_plain[0]["seconds"], 3),
+                                        "step2_seconds": round(st_plain[1]["seconds"], 3)},
+            "speedup_vs_f64_plain": round(t_plain / (total / args.steps), 2),
+        }
+
+    if not args.no_cpu:
+        s1_iter, s1_sweep, s2_iter, s2_sweep, nsub, spent = cpu_baseline(n, args.sigma, args.layout)
+        t_full = args.sweeps * nsub * ((s1_sweep + args.inner * s1_iter) + (s2_sweep + args.inner * s2_iter))
+        out["cpu_baseline"] = {
+            "value": round(pix_iters / t_full / 1e6, 3), "unit": "Mpix*iter/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"FP64 numpy/scipy oracle, one interior subdomain of the {n}^2 "
+                       f"{args.layout[0]}x{args.layout[1]} workload: Step-1 inner loop (Alg. 5) at 1 "
+                       "and 2 iterations, Step-2 inner loop (Alg. 3) at 1 and 3 iterations, scaled "
+                       f"to {args.sweeps} sweeps x {args.inner} inner x {nsub} subdomains; "
+                       f"{spent:.1f} s of CPU time, single thread"),
+            "seconds_full_workload_estimate": round(t_full, 1),
+        }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -71,7 +71,7 @@ typedef enum { TVS_IRV2 = 0, TVS_IRV1 = 1 } tvs_variant;
 /* Model and iteration parameters.
  *   delta  > 0      TFS weight (eq. eq:cTFS)
  *   alpha  > 0      Step-2 weight (eq. modifiedStep2; IRV1: alpha = 1/mu)
- *   t in (0, 1/8]   dual step size (Algorithm 1 and Theorem 3)
+ *   t in (0, 1/8]   dual step size (Algorithm 1 and the convergence theorem after it)
  *   h      > 0      mesh size (the paper's experiments use h = 1)
  *   eps    > 0      IRV1 smoothing of |tau^perp| (eq. eq:defXi2); unused by IRV2
  *   variant         TVS_IRV2 or TVS_IRV1 */
@@ -159,6 +159,25 @@ int tvs_schwarz_solve(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dt
  * Omega-tilde. */
 int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dtype dtype,
                          double h, void* u_out, void* stream);
+
+/* Diagnostics: kernel timing.  While enabled, every launch of an
+ * instrumented kernel class is bracketed by two HIP events recorded on the
+ * call's stream, and credited with the launch's algorithmic bytes (the data
+ * the kernel must read and write at minimum; the formulas are listed with
+ * each kernel in the library sources).  Enabling it adds two event records
+ * per instrumented launch and no synchronisation.
+ *   tvs_timing_enable  switch recording on (1) or off (0)
+ *   tvs_timing_reset   drop everything recorded so far
+ *   tvs_timing_count   wait for the recorded events and return the number of
+ *                      kernel classes (>= 0), or a negative error code
+ *   tvs_timing_get     entry i (0 <= i < count): class name copied into
+ *                      name[name_len], launches, total milliseconds, total
+ *                      algorithmic bytes */
+int tvs_timing_enable(tvs_ctx* ctx, int enable);
+int tvs_timing_reset(tvs_ctx* ctx);
+int tvs_timing_count(tvs_ctx* ctx);
+int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* launches, double* ms,
+                   double* bytes);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // C-ABI entry points of libtvs (include/tvs.h) and the host orchestration of
 // Algorithm 2 for both TV-Stokes steps.
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -59,6 +60,7 @@ struct SubSet {
   std::vector<SubDesc> subs;
   DevBuf subs_d;
   SubFrames sf{};
+  double sub_px = 0;  // sum of subdomain sizes (points)
 };
 
 // Step 1 subdomains on Omega-tilde: s = the subdomain, a = grown by one
@@ -81,6 +83,7 @@ void build_subs1(SubSet& ss, int n2, int n1, hipStream_t s) {
       d.m1 = b;
       fr = std::max(fr, d.bi);
       fp = std::max(fp, d.bj);
+      ss.sub_px += double(d.si) * d.sj;
       ss.subs.push_back(d);
     }
   ss.subs_d.alloc(sizeof(SubDesc) * ss.subs.size());
@@ -115,6 +118,7 @@ void build_subs2(SubSet& ss, int N2, int N1, hipStream_t s) {
       d.m1 = b;
       fr = std::max(fr, d.ai);
       fp = std::max(fp, d.aj);
+      ss.sub_px += double(d.si) * d.sj;
       ss.subs.push_back(d);
     }
   ss.subs_d.alloc(sizeof(SubDesc) * ss.subs.size());
@@ -168,6 +172,7 @@ struct tvs_ctx {
   std::map<tvs::GridKey, std::unique_ptr<tvs::GreenPlan<float>>> projf;
   std::map<tvs::GridKey, std::unique_ptr<tvs::GreenPlan<double>>> projd;
   std::map<tvs::GridKey, std::unique_ptr<tvs::DevBuf>> projtmp;
+  tvs::KernelTimer timer;
   tvs::DevBuf partials;  // FP64 partial sums
   tvs::DevBuf scal;      // FP64 results (energies per sweep, gap)
   size_t scal_cap = 0;
@@ -351,11 +356,14 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
   T* cur = dptr<T>(P.va);
   T* nxt = dptr<T>(P.vb);
   const double scale = std::sqrt(2.0 * double(gpl));
+  KernelTimer* tm = &c->timer;
+  const double px = P.ss.sub_px, esz = sizeof(T);
+  const char* ltag = P.plain ? "s1_plain" : "s1_local";
   int done = 0;
   for (int n = 0; n < its->sweeps; ++n) {
     // a2: r^n = f - P_K vecdiv p^n (global, once per sweep) and D(p^n)
     launch_global_vecdiv<T>(dptr<T>(P.p), g, inv_h, dptr<T>(P.zg), s);
-    P.global->apply_div(dptr<T>(P.zg), gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s);
+    P.global->apply_div(dptr<T>(P.zg), gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s, tm, "s1_global");
     launch_residual<T>(dptr<T>(P.f1), dptr<T>(P.zg), dptr<T>(P.phig), g, inv_h, dptr<T>(P.r), part, e + n, s);
     if (its->tol > 0 && n >= 1) {
       double hv[2];
@@ -372,13 +380,17 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
     }
     // a3: inner iterations, warm-started from the previous sweep's q_m
     for (int nu = 0; nu < its->inner; ++nu) {
-      launch_sub_vecdiv<T>(sf, g, inv_h, cur, dptr<T>(P.z), s);
-      lp.apply_div(dptr<T>(P.z), f2p, dptr<T>(P.phi), f1p, s);
-      launch_sub_update1<T>(sf, g, cs, cur, dptr<T>(P.z), dptr<T>(P.phi), omega, nxt, s);
+      KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
+                        [&] { launch_sub_vecdiv<T>(sf, g, inv_h, cur, dptr<T>(P.z), s); });
+      lp.apply_div(dptr<T>(P.z), f2p, dptr<T>(P.phi), f1p, s, tm, ltag);
+      KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
+        launch_sub_update1<T>(sf, g, cs, cur, dptr<T>(P.z), dptr<T>(P.phi), omega, nxt, s);
+      });
       std::swap(cur, nxt);
     }
     // a4: p^{n+1} = (1 - ahat) p^n + ahat sum_m q_m
-    launch_combine<T>(sf, g, 4, cs.ahat, cur, dptr<T>(P.p), s);
+    KernelTimer::time(tm, "s1_combine", 4 * esz * (2.0 * gpl + px), s,
+                      [&] { launch_combine<T>(sf, g, 4, cs.ahat, cur, dptr<T>(P.p), s); });
     ++done;
   }
   // a5: tau = delta (f - P_K vecdiv p), D(p^S) and the gap
@@ -429,6 +441,8 @@ void run_step2(tvs_ctx* c, const T* d0, const T* tau, int N2, int N1, const tvs_
   T* cur = dptr<T>(P.va);
   T* nxt = dptr<T>(P.vb);
   const double scale = std::sqrt(double(gpl));
+  KernelTimer* tm = &c->timer;
+  const double px = P.ss.sub_px, esz = sizeof(T);
   int done = 0;
   for (int n = 0; n < its->sweeps; ++n) {
     launch_energy_rof<T>(dptr<T>(P.p), dptr<T>(P.f2), g, inv_h, part, e + n, s);
@@ -442,11 +456,13 @@ void run_step2(tvs_ctx* c, const T* d0, const T* tau, int N2, int N1, const tvs_
     launch_sub2_prologue<T>(sf, g, inv_h, dptr<T>(P.p), dptr<T>(P.f2), dptr<T>(P.b), s);
     // a8: inner iterations
     for (int nu = 0; nu < its->inner; ++nu) {
-      launch_sub2_update<T>(sf, g, cs, cur, dptr<T>(P.b), nxt, s);
+      KernelTimer::time(tm, "s2_update", 5 * esz * px, s,
+                        [&] { launch_sub2_update<T>(sf, g, cs, cur, dptr<T>(P.b), nxt, s); });
       std::swap(cur, nxt);
     }
     // a9: combine
-    launch_combine<T>(sf, g, 2, cs.ahat, cur, dptr<T>(P.p), s);
+    KernelTimer::time(tm, "s2_combine", 2 * esz * (2.0 * gpl + px), s,
+                      [&] { launch_combine<T>(sf, g, 2, cs.ahat, cur, dptr<T>(P.p), s); });
     ++done;
   }
   launch_energy_rof<T>(dptr<T>(P.p), dptr<T>(P.f2), g, inv_h, part, e + done, s);
@@ -644,6 +660,47 @@ int tvs_schwarz_solve(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dt
       throw Error(TVS_EINVAL, "unknown dtype");
     }
     if (!tau_out) TVS_HIP(hipStreamSynchronize(s));  // before the owned buffer is released
+  });
+}
+
+int tvs_timing_enable(tvs_ctx* ctx, int enable) {
+  return guarded([&] {
+    if (!ctx) throw Error(TVS_EINVAL, "NULL context");
+    ctx->timer.on = enable != 0;
+  });
+}
+
+int tvs_timing_reset(tvs_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) throw Error(TVS_EINVAL, "NULL context");
+    DeviceGuard dg(ctx->device);
+    ctx->timer.reset();
+  });
+}
+
+int tvs_timing_count(tvs_ctx* ctx) {
+  if (!ctx) return TVS_EINVAL;
+  int n = 0;
+  const int rc = guarded([&] {
+    DeviceGuard dg(ctx->device);
+    ctx->timer.collect();
+    n = int(ctx->timer.accs.size());
+  });
+  return rc == TVS_OK ? n : rc;
+}
+
+int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* launches, double* ms,
+                   double* bytes) {
+  return guarded([&] {
+    if (!ctx || !name || name_len < 1 || !launches || !ms || !bytes) throw Error(TVS_EINVAL, "NULL argument");
+    DeviceGuard dg(ctx->device);
+    ctx->timer.collect();
+    if (i < 0 || i >= int(ctx->timer.accs.size())) throw Error(TVS_EINVAL, "no such timing entry");
+    const auto& kv = ctx->timer.accs[size_t(i)];
+    std::snprintf(name, size_t(name_len), "%s", kv.first.c_str());
+    *launches = kv.second.launches;
+    *ms = kv.second.ms;
+    *bytes = kv.second.bytes;
   });
 }
 

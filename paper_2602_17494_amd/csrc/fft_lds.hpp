@@ -1,6 +1,6 @@
 // Mixed-radix (2, 3, 4, 5) Stockham FFT held entirely in LDS.
 //
-// A workgroup of kFftThreads threads transforms `batch` independent complex
+// A workgroup of NT threads transforms `batch` independent complex
 // sequences of length n stored in LDS at buf + b * stride.  Each pass reads
 // all of its butterfly inputs into registers, synchronises, and writes the
 // outputs to their self-sorting positions (Stockham autosort), so one LDS
@@ -13,12 +13,15 @@
 
 namespace tvs {
 
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 256;       // workgroup size for short transforms
+constexpr int kFftThreadsLong = 1024;  // workgroup size for long transforms
 
-// Elements per thread the register staging can hold for one pass.
-template <typename T> struct FftCap;
-template <> struct FftCap<float> { static constexpr int elems = 48; };
-template <> struct FftCap<double> { static constexpr int elems = 24; };
+// Elements per thread the register staging can hold for one pass, kept
+// small so that several workgroups share a CU (about 100 VGPRs).  The
+// 1024-thread float variant holds a little more so that one workgroup can
+// transform sequences up to 10240 points.
+template <typename T, int NT> struct FftCap { static constexpr int elems = 8; };
+template <> struct FftCap<float, 1024> { static constexpr int elems = 10; };
 
 template <int R, typename T>
 __device__ __forceinline__ void butterfly(cplx<T>* v, bool inv) {
@@ -68,18 +71,18 @@ __device__ __forceinline__ void butterfly(cplx<T>* v, bool inv) {
   }
 }
 
-template <typename T, int R>
+template <typename T, int NT, int R>
 __device__ __forceinline__ void fft_pass(cplx<T>* buf, int n, int stride, int batch, int Ls,
                                          const cplx<T>* __restrict__ tw, bool inv) {
   using C = cplx<T>;
-  constexpr int MAXB = (FftCap<T>::elems + R - 1) / R;
+  constexpr int MAXB = (FftCap<T, NT>::elems + R - 1) / R;
   const int nbf = n / R;
   const int total = nbf * batch;
   const int twstep = n / (Ls * R);
   C v[MAXB][R];
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
-    const int jj = threadIdx.x + s * kFftThreads;
+    const int jj = threadIdx.x + s * NT;
     if (jj < total) {
       const int b = jj / nbf;
       const int j = jj - b * nbf;
@@ -101,7 +104,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int n, int stride, int ba
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
-    const int jj = threadIdx.x + s * kFftThreads;
+    const int jj = threadIdx.x + s * NT;
     if (jj < total) {
       const int b = jj / nbf;
       const int j = jj - b * nbf;
@@ -116,18 +119,18 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int n, int stride, int ba
 }
 
 // Transform `batch` sequences of length d.n in LDS (sequence b at
-// buf + b * stride).  Requires batch * d.n <= kFftThreads * FftCap<T>::elems.
-template <typename T>
+// buf + b * stride).  Requires batch * d.n <= NT * FftCap<T, NT>::elems.
+template <typename T, int NT>
 __device__ void fft_lds(cplx<T>* buf, const FftDesc& d, int stride, int batch,
                         const cplx<T>* __restrict__ tw, bool inv) {
   int Ls = 1;
   for (int p = 0; p < d.npass; ++p) {
     const int R = d.radix[p];
     switch (R) {
-      case 4: fft_pass<T, 4>(buf, d.n, stride, batch, Ls, tw, inv); break;
-      case 2: fft_pass<T, 2>(buf, d.n, stride, batch, Ls, tw, inv); break;
-      case 3: fft_pass<T, 3>(buf, d.n, stride, batch, Ls, tw, inv); break;
-      default: fft_pass<T, 5>(buf, d.n, stride, batch, Ls, tw, inv); break;
+      case 4: fft_pass<T, NT, 4>(buf, d.n, stride, batch, Ls, tw, inv); break;
+      case 2: fft_pass<T, NT, 2>(buf, d.n, stride, batch, Ls, tw, inv); break;
+      case 3: fft_pass<T, NT, 3>(buf, d.n, stride, batch, Ls, tw, inv); break;
+      default: fft_pass<T, NT, 5>(buf, d.n, stride, batch, Ls, tw, inv); break;
     }
     Ls *= R;
   }

@@ -166,12 +166,13 @@ __device__ __forceinline__ double g_lookup(const double* __restrict__ g, int n2,
 
 // Forward FFT along x of the real windows K(m_i, m_j) = G(bi + d(m_i),
 // bj + d(m_j)), d(m) = m below ceil(L/2) and m - L above (the offsets a
-// linear convolution of a box with itself needs).
-__global__ __launch_bounds__(kFftThreads) void k_spec_rows(const double* __restrict__ g, int n2,
-                                                           int n1, const int4* __restrict__ keys,
-                                                           int Li, int Lj, FftDesc fj,
-                                                           const cplx<double>* __restrict__ twj,
-                                                           cplx<double>* __restrict__ out, int ppw) {
+// linear convolution of a box with itself needs).  Output row-major
+// [slot][m_i][k_j].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_spec_rows(const double* __restrict__ g, int n2, int n1,
+                                                  const int4* __restrict__ keys, int Li, int Lj,
+                                                  FftDesc fj, const cplx<double>* __restrict__ twj,
+                                                  cplx<double>* __restrict__ out, int ppw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
   const int slot = blockIdx.y;
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_rows(const double* __restr
   const int Lh = Lj / 2 + 1;
   const int hi_i = (Li + 1) / 2, hi_j = (Lj + 1) / 2;
   const int q0 = blockIdx.x * ppw;
-  for (int e = threadIdx.x; e < ppw * Lj; e += kFftThreads) {
+  for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
     const int qq = e / Lj, c = e - qq * Lj;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const long long dj = c < hi_j ? c : c - Lj;
@@ -189,8 +190,8 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_rows(const double* __restr
     buf[qq * Lj + c] = cplx<double>{va, vb};
   }
   __syncthreads();
-  fft_lds<double>(buf, fj, Lj, ppw, twj, false);
-  for (int e = threadIdx.x; e < ppw * Lh; e += kFftThreads) {
+  fft_lds<double, NT>(buf, fj, Lj, ppw, twj, false);
+  for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int qq = e / Lh, k = e - qq * Lh;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const cplx<double> z = buf[qq * Lj + k];
@@ -202,45 +203,45 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_rows(const double* __restr
 }
 
 // Forward FFT along y, then the flip phases and the 1/(Li Lj) normalisation
-// of the inverse transforms are folded in; output in T.
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_spec_cols(const cplx<double>* __restrict__ in,
-                                                           const int4* __restrict__ keys, int Li,
-                                                           int Lj, FftDesc fi,
-                                                           const cplx<double>* __restrict__ twi,
-                                                           const cplx<double>* __restrict__ twj,
-                                                           cplx<T>* __restrict__ out, int cpw) {
+// of the inverse transforms are folded in; output in T, column-major
+// [slot][k_j][k_i].
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_spec_cols(const cplx<double>* __restrict__ in,
+                                                  const int4* __restrict__ keys, int Li, int Lj,
+                                                  FftDesc fi, const cplx<double>* __restrict__ twi,
+                                                  const cplx<double>* __restrict__ twj,
+                                                  cplx<T>* __restrict__ out, int cpw) {
   extern __shared__ unsigned char smem_raw[];
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
   const int slot = blockIdx.y;
   const int4 key = keys[slot];
   const int Lh = Lj / 2 + 1;
-  const int cs = Li + 1;
   const int k0 = blockIdx.x * cpw;
   const size_t base = static_cast<size_t>(slot) * Li * Lh;
-  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
+  for (int e = threadIdx.x; e < cpw * Li; e += NT) {
     const int r = e / cpw, c = e - r * cpw;
     const int k = k0 + c;
-    buf[c * cs + r] = (k < Lh) ? in[base + static_cast<size_t>(r) * Lh + k] : cplx<double>{0.0, 0.0};
+    buf[c * Li + r] = (k < Lh) ? in[base + static_cast<size_t>(r) * Lh + k] : cplx<double>{0.0, 0.0};
   }
   __syncthreads();
-  fft_lds<double>(buf, fi, cs, cpw, twi, false);
+  fft_lds<double, NT>(buf, fi, Li, cpw, twi, false);
   const double scale = 1.0 / (double(Li) * double(Lj));
-  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
-    const int r = e / cpw, c = e - r * cpw;
+  for (int e = threadIdx.x; e < cpw * Li; e += NT) {
+    const int c = e / Li, r = e - c * Li;
     const int k = k0 + c;
     if (k >= Lh) continue;
-    cplx<double> v = buf[c * cs + r];
+    cplx<double> v = buf[c * Li + r];
     v.x *= scale;
     v.y *= scale;
     if (key.z >= 0) v = cmul(v, twi[(static_cast<long long>(r) * key.z) % Li]);
     if (key.w >= 0) v = cmul(v, twj[(static_cast<long long>(k) * key.w) % Lj]);
-    out[base + static_cast<size_t>(r) * Lh + k] = cplx<T>{T(v.x), T(v.y)};
+    out[base + static_cast<size_t>(k) * Li + r] = cplx<T>{T(v.x), T(v.y)};
   }
 }
 
 // ---------------------------------------------------------------------------
-// Apply kernels
+// Apply kernels.  The half spectra are kept column-major per box,
+// S[b][k_j][row], so that the column transforms read contiguous data.
 // ---------------------------------------------------------------------------
 
 // div of a 2-plane frame field at local (r, q) of box b, with the boundary
@@ -259,18 +260,18 @@ __device__ __forceinline__ T div_at(const T* __restrict__ u, const Frame& f, int
   return ((a - am) + (c - cm)) * inv_h;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
-                                                                Frame uf) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
+                                                       Frame uf) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.y;
   const GreenBox bx = d.boxes[b];
-  const int Lj = d.Lj, Lh = d.Lh;
-  const int q0 = blockIdx.x * d.ppw;
+  const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
+  const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
-  for (int e = threadIdx.x; e < d.ppw * Lj; e += kFftThreads) {
+  for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
     const int qq = e / Lj, c = e - qq * Lj;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     T va = T(0), vb = T(0);
@@ -281,54 +282,55 @@ __global__ __launch_bounds__(kFftThreads) void k_green_rows_fwd(GreenDev<T> d, c
     buf[qq * Lj + c] = C{va, vb};
   }
   __syncthreads();
-  fft_lds<T>(buf, d.fj, Lj, d.ppw, d.tw_j, false);
+  fft_lds<T, NT>(buf, d.fj, Lj, ppw, d.tw_j, false);
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
-  for (int e = threadIdx.x; e < d.ppw * Lh; e += kFftThreads) {
-    const int qq = e / Lh, k = e - qq * Lh;
+  for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
+    const int k = e / ppw, qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const C z = buf[qq * Lj + k];
     const C zn = buf[qq * Lj + (k == 0 ? 0 : Lj - k)];
-    if (ra < bx.ni) S[static_cast<size_t>(ra) * Lh + k] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
-    if (rb < bx.ni) S[static_cast<size_t>(rb) * Lh + k] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
+    C* col = S + static_cast<size_t>(k) * d.rows_max;
+    if (ra < bx.ni) col[ra] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
+    if (rb < bx.ni) col[rb] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_green_cols(GreenDev<T> d) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   using C = cplx<T>;
-  constexpr int E = FftCap<T>::elems;
+  constexpr int MAXS = FftCap<T, NT>::elems;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.y;
   const GreenBox bx = d.boxes[b];
   const int Li = d.Li, Lh = d.Lh, cpw = d.cpw;
-  const int cs = Li + 1;
   const int k0 = blockIdx.x * cpw;
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
-  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
-    const int r = e / cpw, c = e - r * cpw;
+  for (int e = threadIdx.x; e < cpw * Li; e += NT) {
+    const int c = e / Li, r = e - c * Li;
     const int k = k0 + c;
-    buf[c * cs + r] = (r < bx.ni && k < Lh) ? S[static_cast<size_t>(r) * Lh + k] : C{T(0), T(0)};
+    buf[c * Li + r] = (r < bx.ni && k < Lh) ? S[static_cast<size_t>(k) * d.rows_max + r] : C{T(0), T(0)};
   }
   __syncthreads();
-  fft_lds<T>(buf, d.fi, cs, cpw, d.tw_i, false);
+  fft_lds<T, NT>(buf, d.fi, Li, cpw, d.tw_i, false);
   // Phi = X K00 + conj(X(-ki)) K01 + X(-ki) K10 + conj(X) K11
-  const C* s00 = d.spec + static_cast<size_t>(bx.k00) * Li * Lh;
-  const C* s01 = d.spec + static_cast<size_t>(bx.k01) * Li * Lh;
-  const C* s10 = d.spec + static_cast<size_t>(bx.k10) * Li * Lh;
-  const C* s11 = d.spec + static_cast<size_t>(bx.k11) * Li * Lh;
-  C res[E];
+  const size_t slot_sz = static_cast<size_t>(Li) * Lh;
+  const C* s00 = d.spec + static_cast<size_t>(bx.k00) * slot_sz;
+  const C* s01 = d.spec + static_cast<size_t>(bx.k01) * slot_sz;
+  const C* s10 = d.spec + static_cast<size_t>(bx.k10) * slot_sz;
+  const C* s11 = d.spec + static_cast<size_t>(bx.k11) * slot_sz;
+  C res[MAXS];
 #pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int e = threadIdx.x + s * kFftThreads;
+  for (int s = 0; s < MAXS; ++s) {
+    const int e = threadIdx.x + s * NT;
     if (e < cpw * Li) {
-      const int ki = e / cpw, c = e - ki * cpw;
+      const int c = e / Li, ki = e - c * Li;
       const int k = k0 + c;
-      C x = buf[c * cs + ki];
-      C xn = buf[c * cs + (ki == 0 ? 0 : Li - ki)];
+      const C x = buf[c * Li + ki];
+      const C xn = buf[c * Li + (ki == 0 ? 0 : Li - ki)];
       C acc{T(0), T(0)};
       if (k < Lh) {
-        const size_t o = static_cast<size_t>(ki) * Lh + k;
+        const size_t o = static_cast<size_t>(k) * Li + ki;
         acc = cmul(x, s00[o]);
         acc = cadd(acc, cmul(cconj(xn), s01[o]));
         acc = cadd(acc, cmul(xn, s10[o]));
@@ -339,47 +341,44 @@ __global__ __launch_bounds__(kFftThreads) void k_green_cols(GreenDev<T> d) {
   }
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int e = threadIdx.x + s * kFftThreads;
-    if (e < cpw * Li) {
-      const int ki = e / cpw, c = e - ki * cpw;
-      buf[c * cs + ki] = res[s];
-    }
+  for (int s = 0; s < MAXS; ++s) {
+    const int e = threadIdx.x + s * NT;
+    if (e < cpw * Li) buf[e] = res[s];
   }
   __syncthreads();
-  fft_lds<T>(buf, d.fi, cs, cpw, d.tw_i, true);
-  for (int e = threadIdx.x; e < cpw * Li; e += kFftThreads) {
-    const int r = e / cpw, c = e - r * cpw;
+  fft_lds<T, NT>(buf, d.fi, Li, cpw, d.tw_i, true);
+  for (int e = threadIdx.x; e < cpw * Li; e += NT) {
+    const int c = e / Li, r = e - c * Li;
     const int k = k0 + c;
-    if (r < bx.ni && k < Lh) S[static_cast<size_t>(r) * Lh + k] = buf[c * cs + r];
+    if (r < bx.ni && k < Lh) S[static_cast<size_t>(k) * d.rows_max + r] = buf[e];
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_green_rows_inv(GreenDev<T> d, T* __restrict__ phi,
-                                                                Frame pf) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restrict__ phi, Frame pf) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.y;
   const GreenBox bx = d.boxes[b];
-  const int Lj = d.Lj, Lh = d.Lh;
-  const int q0 = blockIdx.x * d.ppw;
+  const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
+  const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;
   const C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   const int half = Lj / 2;
-  for (int e = threadIdx.x; e < d.ppw * Lj; e += kFftThreads) {
-    const int qq = e / Lj, k = e - qq * Lj;
+  for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
+    const int k = e / ppw, qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const int kk = k <= half ? k : Lj - k;
-    const C a = ra < bx.ni ? S[static_cast<size_t>(ra) * Lh + kk] : C{T(0), T(0)};
-    const C c = rb < bx.ni ? S[static_cast<size_t>(rb) * Lh + kk] : C{T(0), T(0)};
+    const C* col = S + static_cast<size_t>(kk) * d.rows_max;
+    const C a = ra < bx.ni ? col[ra] : C{T(0), T(0)};
+    const C c = rb < bx.ni ? col[rb] : C{T(0), T(0)};
     buf[qq * Lj + k] = k <= half ? C{a.x - c.y, a.y + c.x} : C{a.x + c.y, c.x - a.y};
   }
   __syncthreads();
-  fft_lds<T>(buf, d.fj, Lj, d.ppw, d.tw_j, true);
+  fft_lds<T, NT>(buf, d.fj, Lj, ppw, d.tw_j, true);
   T* out = phi + b * pf.box_stride;
-  for (int e = threadIdx.x; e < d.ppw * bx.nj; e += kFftThreads) {
+  for (int e = threadIdx.x; e < ppw * bx.nj; e += NT) {
     const int qq = e / bx.nj, c = e - qq * bx.nj;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const C z = buf[qq * Lj + c];
@@ -398,13 +397,24 @@ static void allow_lds(F* f, size_t bytes) {
                                                  static_cast<int>(bytes)));
 }
 
-static int pick_batch(int n, int cap_elems, size_t elem_bytes, int max_batch, size_t max_lds,
-                      int stride_pad) {
-  int b = std::min(max_batch, std::max(1, (kFftThreads * cap_elems) / n));
-  while (b > 1 && size_t(b) * (n + stride_pad) * elem_bytes > max_lds) --b;
-  if (size_t(n) * b > size_t(kFftThreads) * cap_elems)
-    throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
-  if (size_t(b) * (n + stride_pad) * elem_bytes > 160 * 1024)
+// Workgroup size and batch for transforms of length n: 256 threads when one
+// transform fits their register staging, 1024 otherwise; as many transforms
+// per workgroup as fit both the staging and `max_lds` bytes of LDS.
+struct Batch {
+  int nt, batch;
+};
+template <typename T>
+static Batch pick_batch(int n, int max_batch, size_t max_lds) {
+  const size_t elem_bytes = sizeof(cplx<T>);
+  constexpr int cs = FftCap<T, kFftThreads>::elems, cl = FftCap<T, kFftThreadsLong>::elems;
+  Batch b{};
+  int cap = 0;
+  if (n <= kFftThreads * cs) { b.nt = kFftThreads; cap = cs; }
+  else if (n <= kFftThreadsLong * cl) { b.nt = kFftThreadsLong; cap = cl; }
+  else throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
+  b.batch = std::min(max_batch, std::max(1, (b.nt * cap) / n));
+  while (b.batch > 1 && size_t(b.batch) * n * elem_bytes > max_lds) --b.batch;
+  if (size_t(b.batch) * n * elem_bytes > 160 * 1024)
     throw Error(-1, "FFT length " + std::to_string(n) + " does not fit in LDS");
   return b;
 }
@@ -440,6 +450,8 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     if (i0 < 0 || j0 < 0 || ni < 1 || nj < 1 || i0 + ni > n2 || j0 + nj > n1)
       throw Error(-1, "Green box outside the grid");
     GreenBox g{i0, j0, ni, nj, 0, 0, 0, 0};
+    sum_ni_lh_ += double(ni) * (Lj / 2 + 1);
+    sum_box_px_ += double(ni) * nj;
     g.k00 = slot_of({0, 0, -1, -1});
     g.k01 = slot_of({0, 2 * j0 + nj, -1, nj - 1});
     g.k10 = slot_of({2 * i0 + ni, 0, ni - 1, -1});
@@ -463,35 +475,41 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     const size_t per_slot = size_t(Li) * Lh;
     const size_t chunk = std::max<size_t>(1, (size_t(512) << 20) / (per_slot * sizeof(cplx<double>)));
     DevBuf tmp(sizeof(cplx<double>) * std::min(chunk, nslot) * per_slot);
-    const int ppw = pick_batch(Lj, FftCap<double>::elems, sizeof(cplx<double>), 8, 96 * 1024, 0);
-    const int cpw = pick_batch(Li, FftCap<double>::elems, sizeof(cplx<double>), 16, 128 * 1024, 1);
-    const size_t lds_r = size_t(ppw) * Lj * sizeof(cplx<double>);
-    const size_t lds_c = size_t(cpw) * (Li + 1) * sizeof(cplx<double>);
-    allow_lds(k_spec_rows, lds_r);
-    allow_lds(k_spec_cols<T>, lds_c);
+    const Batch br = pick_batch<double>(Lj, 8, 80 * 1024);
+    const Batch bc = pick_batch<double>(Li, 16, 80 * 1024);
+    const size_t lds_r = size_t(br.batch) * Lj * sizeof(cplx<double>);
+    const size_t lds_c = size_t(bc.batch) * Li * sizeof(cplx<double>);
+    auto kr = br.nt == kFftThreads ? k_spec_rows<kFftThreads> : k_spec_rows<kFftThreadsLong>;
+    auto kc = bc.nt == kFftThreads ? k_spec_cols<T, kFftThreads> : k_spec_cols<T, kFftThreadsLong>;
+    allow_lds(kr, lds_r);
+    allow_lds(kc, lds_c);
     for (size_t s0 = 0; s0 < nslot; s0 += chunk) {
       const int ns = int(std::min(chunk, nslot - s0));
-      hipLaunchKernelGGL(k_spec_rows, dim3((Li / 2 + ppw - 1) / ppw, ns), dim3(kFftThreads), lds_r, s,
+      hipLaunchKernelGGL(kr, dim3((Li / 2 + br.batch - 1) / br.batch, ns), dim3(br.nt), lds_r, s,
                          table.g.as<double>(), n2, n1, keys_d.as<int4>() + s0, Li, Lj, fj,
-                         tw_j64.as<cplx<double>>(), tmp.as<cplx<double>>(), ppw);
+                         tw_j64.as<cplx<double>>(), tmp.as<cplx<double>>(), br.batch);
       TVS_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_spec_cols<T>, dim3((Lh + cpw - 1) / cpw, ns), dim3(kFftThreads), lds_c, s,
+      hipLaunchKernelGGL(kc, dim3((Lh + bc.batch - 1) / bc.batch, ns), dim3(bc.nt), lds_c, s,
                          tmp.as<cplx<double>>(), keys_d.as<int4>() + s0, Li, Lj, fi,
                          tw_i64.as<cplx<double>>(), tw_j64.as<cplx<double>>(),
-                         spec_.as<cplx<T>>() + s0 * per_slot, cpw);
+                         spec_.as<cplx<T>>() + s0 * per_slot, bc.batch);
       TVS_LAUNCH_CHECK();
     }
     TVS_HIP(hipStreamSynchronize(s));
   }
 
+  const Batch br = pick_batch<T>(Lj, 8, 80 * 1024);
+  const Batch bc = pick_batch<T>(Li, 16, 80 * 1024);
+  nt_rows_ = br.nt;
+  nt_cols_ = bc.nt;
   dev_.n2 = n2;
   dev_.n1 = n1;
   dev_.Li = Li;
   dev_.Lj = Lj;
   dev_.Lh = Lh;
   dev_.rows_max = rows_max;
-  dev_.ppw = pick_batch(Lj, FftCap<T>::elems, sizeof(cplx<T>), 8, 96 * 1024, 0);
-  dev_.cpw = pick_batch(Li, FftCap<T>::elems, sizeof(cplx<T>), 16, 128 * 1024, 1);
+  dev_.ppw = br.batch;
+  dev_.cpw = bc.batch;
   dev_.inv_h = T(1) / T(table.h);
   dev_.boxes = boxes_d_.as<GreenBox>();
   dev_.tw_i = tw_i_.as<cplx<T>>();
@@ -500,9 +518,14 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   dev_.spec = spec_.as<cplx<T>>();
   dev_.fi = fi;
   dev_.fj = fj;
-  allow_lds(k_green_rows_fwd<T>, size_t(dev_.ppw) * Lj * sizeof(cplx<T>));
-  allow_lds(k_green_rows_inv<T>, size_t(dev_.ppw) * Lj * sizeof(cplx<T>));
-  allow_lds(k_green_cols<T>, size_t(dev_.cpw) * (Li + 1) * sizeof(cplx<T>));
+  const size_t lds_r = size_t(dev_.ppw) * Lj * sizeof(cplx<T>);
+  const size_t lds_c = size_t(dev_.cpw) * Li * sizeof(cplx<T>);
+  allow_lds(k_green_rows_fwd<T, kFftThreads>, lds_r);
+  allow_lds(k_green_rows_fwd<T, kFftThreadsLong>, lds_r);
+  allow_lds(k_green_rows_inv<T, kFftThreads>, lds_r);
+  allow_lds(k_green_rows_inv<T, kFftThreadsLong>, lds_r);
+  allow_lds(k_green_cols<T, kFftThreads>, lds_c);
+  allow_lds(k_green_cols<T, kFftThreadsLong>, lds_c);
 }
 
 template <typename T>
@@ -510,18 +533,52 @@ size_t GreenPlan<T>::bytes() const {
   return spec_.bytes + S_.bytes + boxes_d_.bytes + tw_i_.bytes + tw_j_.bytes;
 }
 
+// Algorithmic bytes: the row passes read the source field (2 planes) of
+// every box and write its half spectrum (rows x (Lj/2+1) complex), or the
+// reverse with one output plane; the column pass reads and writes the half
+// spectra and reads every distinct window spectrum once.
 template <typename T>
-void GreenPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t s) {
+double GreenPlan<T>::bytes_rows_fwd() const {
+  return sum_box_px_ * 2 * sizeof(T) + sum_ni_lh_ * sizeof(cplx<T>);
+}
+template <typename T>
+double GreenPlan<T>::bytes_cols() const {
+  return 2 * sum_ni_lh_ * sizeof(cplx<T>) + double(nslot) * Li * dev_.Lh * sizeof(cplx<T>);
+}
+template <typename T>
+double GreenPlan<T>::bytes_rows_inv() const {
+  return sum_ni_lh_ * sizeof(cplx<T>) + sum_box_px_ * sizeof(T);
+}
+
+template <typename T>
+void GreenPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t s,
+                             KernelTimer* timer, const char* tag) {
   const size_t lds_r = size_t(dev_.ppw) * Lj * sizeof(cplx<T>);
-  const size_t lds_c = size_t(dev_.cpw) * (Li + 1) * sizeof(cplx<T>);
+  const size_t lds_c = size_t(dev_.cpw) * Li * sizeof(cplx<T>);
   const int row_groups = ((rows_max + 1) / 2 + dev_.ppw - 1) / dev_.ppw;
-  hipLaunchKernelGGL(k_green_rows_fwd<T>, dim3(row_groups, nbox), dim3(kFftThreads), lds_r, s, dev_, u, uf);
-  TVS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_green_cols<T>, dim3((dev_.Lh + dev_.cpw - 1) / dev_.cpw, nbox), dim3(kFftThreads),
-                     lds_c, s, dev_);
-  TVS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_green_rows_inv<T>, dim3(row_groups, nbox), dim3(kFftThreads), lds_r, s, dev_, phi, pf);
-  TVS_LAUNCH_CHECK();
+  const dim3 gr(row_groups, nbox), gc((dev_.Lh + dev_.cpw - 1) / dev_.cpw, nbox);
+  const std::string t(tag);
+  KernelTimer::time(timer, (t + "_rows_fwd").c_str(), bytes_rows_fwd(), s, [&] {
+    if (nt_rows_ == kFftThreads)
+      hipLaunchKernelGGL((k_green_rows_fwd<T, kFftThreads>), gr, dim3(kFftThreads), lds_r, s, dev_, u, uf);
+    else
+      hipLaunchKernelGGL((k_green_rows_fwd<T, kFftThreadsLong>), gr, dim3(kFftThreadsLong), lds_r, s, dev_, u, uf);
+    TVS_LAUNCH_CHECK();
+  });
+  KernelTimer::time(timer, (t + "_cols").c_str(), bytes_cols(), s, [&] {
+    if (nt_cols_ == kFftThreads)
+      hipLaunchKernelGGL((k_green_cols<T, kFftThreads>), gc, dim3(kFftThreads), lds_c, s, dev_);
+    else
+      hipLaunchKernelGGL((k_green_cols<T, kFftThreadsLong>), gc, dim3(kFftThreadsLong), lds_c, s, dev_);
+    TVS_LAUNCH_CHECK();
+  });
+  KernelTimer::time(timer, (t + "_rows_inv").c_str(), bytes_rows_inv(), s, [&] {
+    if (nt_rows_ == kFftThreads)
+      hipLaunchKernelGGL((k_green_rows_inv<T, kFftThreads>), gr, dim3(kFftThreads), lds_r, s, dev_, phi, pf);
+    else
+      hipLaunchKernelGGL((k_green_rows_inv<T, kFftThreadsLong>), gr, dim3(kFftThreadsLong), lds_r, s, dev_, phi, pf);
+    TVS_LAUNCH_CHECK();
+  });
 }
 
 template class GreenPlan<float>;

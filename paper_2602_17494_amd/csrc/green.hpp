@@ -75,7 +75,10 @@ class GreenPlan {
   // phi = R_B (Delta)^dagger E_B div(u) on every box B, where u is a 2-plane
   // field (x- and y-component) stored in frame `uf` with zeros outside its
   // support, and div uses the grid's boundary rules (Section 4.1).
-  void apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t stream);
+  void apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t stream,
+                 KernelTimer* timer = nullptr, const char* tag = "green");
+  // algorithmic bytes of one launch of each pass
+  double bytes_rows_fwd() const, bytes_cols() const, bytes_rows_inv() const;
 
   int n2, n1, nbox, Li, Lj;
   int rows_max, cols_max;
@@ -84,6 +87,8 @@ class GreenPlan {
 
  private:
   GreenDev<T> dev_{};
+  int nt_rows_ = 0, nt_cols_ = 0;
+  double sum_ni_lh_ = 0, sum_box_px_ = 0;
   DevBuf boxes_d_, tw_i_, tw_j_, spec_, S_;
 };
 

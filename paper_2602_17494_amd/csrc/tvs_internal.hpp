@@ -93,6 +93,83 @@ struct DevBuf {
 template <typename U> U* dptr(const DevBuf& b) { return static_cast<U*>(b.p); }
 
 // ---------------------------------------------------------------------------
+// optional kernel timing: HIP events recorded around instrumented launches
+// on the launch stream, each with the launch's algorithmic bytes
+// ---------------------------------------------------------------------------
+struct KernelTimer {
+  struct Rec {
+    hipEvent_t a, b;
+    double bytes;
+  };
+  struct Acc {
+    std::vector<Rec> pending;
+    long long launches = 0;
+    double ms = 0, bytes = 0;
+  };
+  bool on = false;
+  std::vector<std::pair<std::string, Acc>> accs;
+  std::vector<hipEvent_t> pool;
+
+  Acc& acc(const std::string& name) {
+    for (auto& kv : accs)
+      if (kv.first == name) return kv.second;
+    accs.emplace_back(name, Acc{});
+    return accs.back().second;
+  }
+  hipEvent_t get_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) throw Error(-3, "hipEventCreate failed");
+    return e;
+  }
+  // Wrap a launch: timer may be null or off.
+  template <typename F>
+  static void time(KernelTimer* t, const char* name, double bytes, hipStream_t s, F&& launch) {
+    if (!t || !t->on) {
+      launch();
+      return;
+    }
+    Rec r{t->get_event(), t->get_event(), bytes};
+    if (hipEventRecord(r.a, s) != hipSuccess) throw Error(-3, "hipEventRecord failed");
+    launch();
+    if (hipEventRecord(r.b, s) != hipSuccess) throw Error(-3, "hipEventRecord failed");
+    t->acc(name).pending.push_back(r);
+  }
+  // Fold finished records into the totals (waits for their events).
+  void collect() {
+    for (auto& kv : accs) {
+      for (auto& r : kv.second.pending) {
+        if (hipEventSynchronize(r.b) != hipSuccess) throw Error(-3, "hipEventSynchronize failed");
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) throw Error(-3, "hipEventElapsedTime failed");
+        kv.second.ms += ms;
+        kv.second.bytes += r.bytes;
+        kv.second.launches += 1;
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+      }
+      kv.second.pending.clear();
+    }
+  }
+  void reset() {
+    collect();
+    accs.clear();
+  }
+  ~KernelTimer() {
+    for (auto& kv : accs)
+      for (auto& r : kv.second.pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+      }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// ---------------------------------------------------------------------------
 // one axis of a subdomain layout (Section 6.1)
 // ---------------------------------------------------------------------------
 constexpr int kMaxSub = 32;  // subdomains per axis

@@ -77,12 +77,22 @@ def load():
     lib.tvs_schwarz_solve.restype = ci
     lib.tvs_project_div_free.argtypes = [vp, vp, ci, ci, ci, cd, vp, vp]
     lib.tvs_project_div_free.restype = ci
+    lib.tvs_timing_enable.argtypes = [vp, ci]
+    lib.tvs_timing_enable.restype = ci
+    lib.tvs_timing_reset.argtypes = [vp]
+    lib.tvs_timing_reset.restype = ci
+    lib.tvs_timing_count.argtypes = [vp]
+    lib.tvs_timing_count.restype = ci
+    lib.tvs_timing_get.argtypes = [vp, ci, ctypes.c_char_p, ci, ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(cd), ctypes.POINTER(cd)]
+    lib.tvs_timing_get.restype = ci
     _lib = lib
     return lib
 
 
 EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_bytes", "tvs_step1",
-            "tvs_step2", "tvs_schwarz_solve", "tvs_project_div_free"]
+            "tvs_step2", "tvs_schwarz_solve", "tvs_project_div_free", "tvs_timing_enable",
+            "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get"]
 
 
 def _check(code):
@@ -189,6 +199,28 @@ class Context:
                                         ctypes.byref(iters), _dev(d_out, (n2, n1), d0.dtype),
                                         tau_p, st if stats else None, _stream(d0.device)))
         return d_out, ([st[0].as_dict(), st[1].as_dict()] if stats else None)
+
+    def timing(self, enable=True):
+        """Switch kernel timing on or off (HIP events around instrumented launches)."""
+        _check(load().tvs_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_reset(self):
+        _check(load().tvs_timing_reset(self._h))
+
+    def timing_read(self):
+        """{kernel class: (launches, total ms, total algorithmic bytes)}"""
+        lib = load()
+        n = lib.tvs_timing_count(self._h)
+        if n < 0:
+            _check(n)
+        out = {}
+        buf = ctypes.create_string_buffer(128)
+        for i in range(n):
+            la, ms, by = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+            _check(lib.tvs_timing_get(self._h, i, buf, 128, ctypes.byref(la), ctypes.byref(ms),
+                                      ctypes.byref(by)))
+            out[buf.value.decode()] = (la.value, ms.value, by.value)
+        return out
 
     def project_div_free(self, u, h=1.0, out=None):
         _, n2, n1 = u.shape
