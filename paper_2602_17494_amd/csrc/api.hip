@@ -398,6 +398,11 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
   P.global->apply_div(dptr<T>(P.zg), gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s);
   launch_residual<T>(dptr<T>(P.f1), dptr<T>(P.zg), dptr<T>(P.phig), g, inv_h, dptr<T>(P.r), part, e + done, s);
   launch_scale<T>(dptr<T>(P.r), 2 * gpl, T(prm->delta), tau_out, s);
+  // tau already lies in K; projecting it once more is the identity in exact
+  // arithmetic and removes the small divergence left by rounding, which the
+  // IRV2 row integral of tau_2 would otherwise accumulate across the image
+  P.global->apply_div(tau_out, gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s, tm, "s1_global");
+  launch_f1<T>(tau_out, dptr<T>(P.phig), g, inv_h, T(1), tau_out, s);
   if (st) {
     launch_gap_tfs<T>(tau_out, dptr<T>(P.p), g, inv_h, part, e + its->sweeps + 1, s);
     std::vector<double> hv(size_t(its->sweeps) + 2);
