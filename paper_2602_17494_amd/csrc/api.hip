@@ -42,6 +42,10 @@ AxisLayout make_axis(int n, int m, int s, const char* name) {
   return a;
 }
 
+// frame rows start on 256-byte boundaries (64 float or 32 double columns);
+// pad to 64 columns for both
+int align_pitch(int fp) { return fp > 64 ? (fp + 63) / 64 * 64 : fp; }
+
 double colouring_alpha_hat(int m2, int m1) {
   if (m1 == 1 && m2 == 1) return 1.0;
   if (m1 == 1 || m2 == 1) return 0.5;
@@ -92,7 +96,7 @@ void build_subs1(SubSet& ss, int n2, int n1, hipStream_t s) {
   ss.sf.subs = ss.subs_d.as<SubDesc>();
   ss.sf.nsub = int(ss.subs.size());
   ss.sf.fr = fr;
-  ss.sf.fp = fp;
+  ss.sf.fp = align_pitch(fp);
   ss.sf.plane = (long long)fr * fp;
   ss.sf.ay = ss.ay;
   ss.sf.ax = ss.ax;
@@ -127,7 +131,7 @@ void build_subs2(SubSet& ss, int N2, int N1, hipStream_t s) {
   ss.sf.subs = ss.subs_d.as<SubDesc>();
   ss.sf.nsub = int(ss.subs.size());
   ss.sf.fr = fr;
-  ss.sf.fp = fp;
+  ss.sf.fp = align_pitch(fp);
   ss.sf.plane = (long long)fr * fp;
   ss.sf.ay = ss.ay;
   ss.sf.ax = ss.ax;
@@ -139,11 +143,12 @@ struct Step1Problem {
   SubSet ss;
   bool plain = false;
   std::unique_ptr<GreenPlan<T>> global, local;
-  DevBuf tau0, f1, r, zg, phig, p;     // global arrays on Omega-tilde
-  DevBuf va, vb, vt, z, phi, omega;    // per-subdomain frames
+  DevBuf tau0, f1, r, zg, phig, p;         // global arrays on Omega-tilde
+  DevBuf va, vb, vt, za, zb, zw, phi, omega;  // per-subdomain frames
   size_t bytes() const {
     size_t b = tau0.bytes + f1.bytes + r.bytes + zg.bytes + phig.bytes + p.bytes + va.bytes +
-               vb.bytes + vt.bytes + z.bytes + phi.bytes + omega.bytes + global->bytes();
+               vb.bytes + vt.bytes + za.bytes + zb.bytes + zw.bytes + phi.bytes + omega.bytes +
+               global->bytes();
     if (local) b += local->bytes();
     return b;
   }
@@ -273,9 +278,11 @@ Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layou
   P->vb.alloc(4 * fpb);
   if (!P->plain) {
     P->vt.alloc(4 * fpb);
+    P->zw.alloc(2 * fpb);
     P->omega.alloc(2 * fpb);
   }
-  P->z.alloc(2 * fpb);
+  P->za.alloc(2 * fpb);
+  P->zb.alloc(2 * fpb);
   P->phi.alloc(fpb);
   auto& ref = *P;
   mp[key] = std::move(P);
@@ -355,6 +362,9 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
   const T* omega = P.plain ? dptr<T>(P.f1) : dptr<T>(P.omega);
   T* cur = dptr<T>(P.va);
   T* nxt = dptr<T>(P.vb);
+  T* zcur = dptr<T>(P.za);  // vecdiv of cur (0 for v = 0)
+  T* znxt = dptr<T>(P.zb);
+  launch_fill<T>(zcur, 2 * sf.plane * sf.nsub, T(0), s);
   const double scale = std::sqrt(2.0 * double(gpl));
   KernelTimer* tm = &c->timer;
   const double px = P.ss.sub_px, esz = sizeof(T);
@@ -374,19 +384,21 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
     if (!P.plain) {
       // omega_m = R_{m,+} r^n + LP_m(vecdiv(theta_m p^n))
       launch_sub_theta_p<T>(sf, g, dptr<T>(P.p), 4, dptr<T>(P.vt), s);
-      launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P.vt), dptr<T>(P.z), s);
-      lp.apply_div(dptr<T>(P.z), f2p, dptr<T>(P.phi), f1p, s);
-      launch_sub_omega<T>(sf, g, inv_h, dptr<T>(P.r), dptr<T>(P.z), dptr<T>(P.phi), dptr<T>(P.omega), s);
+      launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P.vt), dptr<T>(P.zw), s);
+      lp.apply_div(dptr<T>(P.zw), f2p, dptr<T>(P.phi), f1p, s, tm, ltag);
+      launch_sub_omega<T>(sf, g, inv_h, dptr<T>(P.r), dptr<T>(P.zw), dptr<T>(P.phi), dptr<T>(P.omega), s);
     }
-    // a3: inner iterations, warm-started from the previous sweep's q_m
+    // a3: inner iterations, warm-started from the previous sweep's q_m:
+    // phi = Delta^+ div z on the Green box, the update of v, z' = vecdiv v'
     for (int nu = 0; nu < its->inner; ++nu) {
-      KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
-                        [&] { launch_sub_vecdiv<T>(sf, g, inv_h, cur, dptr<T>(P.z), s); });
-      lp.apply_div(dptr<T>(P.z), f2p, dptr<T>(P.phi), f1p, s, tm, ltag);
+      lp.apply_div(zcur, f2p, dptr<T>(P.phi), f1p, s, tm, ltag);
       KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
-        launch_sub_update1<T>(sf, g, cs, cur, dptr<T>(P.z), dptr<T>(P.phi), omega, nxt, s);
+        launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P.phi), omega, nxt, s);
       });
+      KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
+                        [&] { launch_sub_vecdiv<T>(sf, g, inv_h, nxt, znxt, s); });
       std::swap(cur, nxt);
+      std::swap(zcur, znxt);
     }
     // a4: p^{n+1} = (1 - ahat) p^n + ahat sum_m q_m
     KernelTimer::time(tm, "s1_combine", 4 * esz * (2.0 * gpl + px), s,

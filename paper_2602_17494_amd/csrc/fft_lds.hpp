@@ -72,22 +72,22 @@ __device__ __forceinline__ void butterfly(cplx<T>* v, bool inv) {
 }
 
 template <typename T, int NT, int R>
-__device__ __forceinline__ void fft_pass(cplx<T>* buf, int n, int stride, int batch, int Ls,
-                                         const cplx<T>* __restrict__ tw, bool inv) {
+__device__ __forceinline__ void fft_pass(cplx<T>* buf, int stride, int batch, FastDiv fls,
+                                         FastDiv fnbf, int twstep, const cplx<T>* __restrict__ tw,
+                                         bool inv) {
   using C = cplx<T>;
   constexpr int MAXB = (FftCap<T, NT>::elems + R - 1) / R;
-  const int nbf = n / R;
+  const int nbf = fnbf.d, Ls = fls.d;
   const int total = nbf * batch;
-  const int twstep = n / (Ls * R);
   C v[MAXB][R];
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
     const int jj = threadIdx.x + s * NT;
     if (jj < total) {
-      const int b = jj / nbf;
+      const int b = fnbf.div(jj);
       const int j = jj - b * nbf;
       const C* x = buf + b * stride;
-      const int k = j % Ls;
+      const int k = j - fls.div(j) * Ls;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         C c = x[j + t * nbf];
@@ -106,11 +106,12 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int n, int stride, int ba
   for (int s = 0; s < MAXB; ++s) {
     const int jj = threadIdx.x + s * NT;
     if (jj < total) {
-      const int b = jj / nbf;
+      const int b = fnbf.div(jj);
       const int j = jj - b * nbf;
       C* y = buf + b * stride;
-      const int k = j % Ls;
-      const int base = (j / Ls) * Ls * R + k;
+      const int g = fls.div(j);
+      const int k = j - g * Ls;
+      const int base = g * Ls * R + k;
 #pragma unroll
       for (int t = 0; t < R; ++t) y[base + t * Ls] = v[s][t];
     }
@@ -123,16 +124,15 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int n, int stride, int ba
 template <typename T, int NT>
 __device__ void fft_lds(cplx<T>* buf, const FftDesc& d, int stride, int batch,
                         const cplx<T>* __restrict__ tw, bool inv) {
-  int Ls = 1;
   for (int p = 0; p < d.npass; ++p) {
-    const int R = d.radix[p];
-    switch (R) {
-      case 4: fft_pass<T, NT, 4>(buf, d.n, stride, batch, Ls, tw, inv); break;
-      case 2: fft_pass<T, NT, 2>(buf, d.n, stride, batch, Ls, tw, inv); break;
-      case 3: fft_pass<T, NT, 3>(buf, d.n, stride, batch, Ls, tw, inv); break;
-      default: fft_pass<T, NT, 5>(buf, d.n, stride, batch, Ls, tw, inv); break;
+    const FastDiv ls = d.ls[p], nb = d.nbf[p];
+    const int ts = d.twstep[p];
+    switch (d.radix[p]) {
+      case 4: fft_pass<T, NT, 4>(buf, stride, batch, ls, nb, ts, tw, inv); break;
+      case 2: fft_pass<T, NT, 2>(buf, stride, batch, ls, nb, ts, tw, inv); break;
+      case 3: fft_pass<T, NT, 3>(buf, stride, batch, ls, nb, ts, tw, inv); break;
+      default: fft_pass<T, NT, 5>(buf, stride, batch, ls, nb, ts, tw, inv); break;
     }
-    Ls *= R;
   }
 }
 

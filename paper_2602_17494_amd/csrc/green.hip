@@ -22,16 +22,36 @@ int smooth_even_at_least(int n) {
   return m;
 }
 
+FastDiv make_fastdiv(int d) {
+  if (d < 1 || d >= (1 << 16)) throw Error(-1, "divisor out of range");
+  FastDiv f{};
+  f.d = d;
+  f.m = d == 1 ? 0u : unsigned(((1ULL << 32) + d - 1) / d);
+  return f;
+}
+
 FftDesc make_fft_desc(int n) {
   FftDesc d{};
   d.n = n;
   int m = n, k = 0;
-  while (m % 4 == 0) { d.radix[k++] = 4; m /= 4; }
-  while (m % 2 == 0) { d.radix[k++] = 2; m /= 2; }
-  while (m % 3 == 0) { d.radix[k++] = 3; m /= 3; }
-  while (m % 5 == 0) { d.radix[k++] = 5; m /= 5; }
-  if (m != 1 || k > kMaxPass) throw Error(-1, "FFT length " + std::to_string(n) + " is not 2^a 3^b 5^c");
+  auto push = [&](int r) {
+    if (k >= kMaxPass) throw Error(-1, "FFT length " + std::to_string(n) + " needs too many passes");
+    d.radix[k++] = r;
+    m /= r;
+  };
+  while (m % 4 == 0) push(4);
+  while (m % 2 == 0) push(2);
+  while (m % 3 == 0) push(3);
+  while (m % 5 == 0) push(5);
+  if (m != 1) throw Error(-1, "FFT length " + std::to_string(n) + " is not 2^a 3^b 5^c");
   d.npass = k;
+  int ls = 1;
+  for (int p = 0; p < k; ++p) {
+    d.ls[p] = make_fastdiv(ls);
+    d.nbf[p] = make_fastdiv(n / d.radix[p]);
+    d.twstep[p] = n / (ls * d.radix[p]);
+    ls *= d.radix[p];
+  }
   return d;
 }
 
@@ -272,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
   for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
-    const int qq = e / Lj, c = e - qq * Lj;
+    const int qq = d.fd_Lj.div(e), c = e - qq * Lj;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     T va = T(0), vb = T(0);
     if (c < bx.nj) {
@@ -285,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   fft_lds<T, NT>(buf, d.fj, Lj, ppw, d.tw_j, false);
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
-    const int k = e / ppw, qq = e - k * ppw;
+    const int k = d.fd_ppw.div(e), qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const C z = buf[qq * Lj + k];
     const C zn = buf[qq * Lj + (k == 0 ? 0 : Lj - k)];
@@ -306,10 +326,11 @@ __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   const int Li = d.Li, Lh = d.Lh, cpw = d.cpw;
   const int k0 = blockIdx.x * cpw;
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
-  for (int e = threadIdx.x; e < cpw * Li; e += NT) {
-    const int c = e / Li, r = e - c * Li;
+  for (int c = 0; c < cpw; ++c) {
     const int k = k0 + c;
-    buf[c * Li + r] = (r < bx.ni && k < Lh) ? S[static_cast<size_t>(k) * d.rows_max + r] : C{T(0), T(0)};
+    const C* col = S + static_cast<size_t>(k) * d.rows_max;
+    for (int r = threadIdx.x; r < Li; r += NT)
+      buf[c * Li + r] = (r < bx.ni && k < Lh) ? col[r] : C{T(0), T(0)};
   }
   __syncthreads();
   fft_lds<T, NT>(buf, d.fi, Li, cpw, d.tw_i, false);
@@ -324,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   for (int s = 0; s < MAXS; ++s) {
     const int e = threadIdx.x + s * NT;
     if (e < cpw * Li) {
-      const int c = e / Li, ki = e - c * Li;
+      const int c = d.fd_Li.div(e), ki = e - c * Li;
       const int k = k0 + c;
       const C x = buf[c * Li + ki];
       const C xn = buf[c * Li + (ki == 0 ? 0 : Li - ki)];
@@ -347,10 +368,11 @@ __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   }
   __syncthreads();
   fft_lds<T, NT>(buf, d.fi, Li, cpw, d.tw_i, true);
-  for (int e = threadIdx.x; e < cpw * Li; e += NT) {
-    const int c = e / Li, r = e - c * Li;
+  for (int c = 0; c < cpw; ++c) {
     const int k = k0 + c;
-    if (r < bx.ni && k < Lh) S[static_cast<size_t>(k) * d.rows_max + r] = buf[e];
+    if (k >= Lh) break;
+    C* col = S + static_cast<size_t>(k) * d.rows_max;
+    for (int r = threadIdx.x; r < bx.ni; r += NT) col[r] = buf[c * Li + r];
   }
 }
 
@@ -367,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   const C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   const int half = Lj / 2;
   for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
-    const int k = e / ppw, qq = e - k * ppw;
+    const int k = d.fd_ppw.div(e), qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const int kk = k <= half ? k : Lj - k;
     const C* col = S + static_cast<size_t>(kk) * d.rows_max;
@@ -378,12 +400,14 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   __syncthreads();
   fft_lds<T, NT>(buf, d.fj, Lj, ppw, d.tw_j, true);
   T* out = phi + b * pf.box_stride;
-  for (int e = threadIdx.x; e < ppw * bx.nj; e += NT) {
-    const int qq = e / bx.nj, c = e - qq * bx.nj;
+  for (int qq = 0; qq < ppw; ++qq) {
     const int ra = 2 * (q0 + qq), rb = ra + 1;
-    const C z = buf[qq * Lj + c];
-    if (ra < bx.ni) out[static_cast<long long>(ra) * pf.pitch + c] = z.x;
-    if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
+    if (ra >= bx.ni) break;
+    for (int c = threadIdx.x; c < bx.nj; c += NT) {
+      const C z = buf[qq * Lj + c];
+      out[static_cast<long long>(ra) * pf.pitch + c] = z.x;
+      if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
+    }
   }
 }
 
@@ -510,6 +534,9 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   dev_.rows_max = rows_max;
   dev_.ppw = br.batch;
   dev_.cpw = bc.batch;
+  dev_.fd_Li = make_fastdiv(Li);
+  dev_.fd_Lj = make_fastdiv(Lj);
+  dev_.fd_ppw = make_fastdiv(br.batch);
   dev_.inv_h = T(1) / T(table.h);
   dev_.boxes = boxes_d_.as<GreenBox>();
   dev_.tw_i = tw_i_.as<cplx<T>>();

@@ -57,6 +57,7 @@ struct GreenDev {
   int Li, Lj, Lh;
   int rows_max;
   int ppw, cpw;
+  FastDiv fd_Li, fd_Lj, fd_ppw;
   T inv_h;
   const GreenBox* boxes;
   const cplx<T>* tw_i;

@@ -144,8 +144,8 @@ __device__ __forceinline__ T dp_global(const T* phi, Grid g, int i, int j, int c
 
 // f = delta^{-1} P_K tau_0 = (tau_0 - grad phi)/delta with phi = Delta^+ div tau_0
 template <typename T>
-__global__ void k_f1(const T* __restrict__ tau0, const T* __restrict__ phi, Grid g, T inv_h,
-                     T inv_delta, T* __restrict__ f1) {
+__global__ void k_f1(const T* tau0, const T* __restrict__ phi, Grid g, T inv_h, T inv_delta,
+                     T* f1) {  // tau0 and f1 may alias (each point is read before it is written)
   const int j = blockIdx.x * kBX + threadIdx.x, i = blockIdx.y * kBY + threadIdx.y;
   if (i >= g.n2 || j >= g.n1) return;
   const long long plane = (long long)g.n2 * g.n1;

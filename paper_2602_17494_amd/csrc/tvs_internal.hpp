@@ -198,12 +198,30 @@ __host__ __device__ __forceinline__ T axis_theta(const AxisLayout& a, int m, int
 // ---------------------------------------------------------------------------
 // FFT plan data passed to kernels by value
 // ---------------------------------------------------------------------------
-constexpr int kMaxPass = 24;
+constexpr int kMaxPass = 16;
+
+// Division by a runtime divisor d (1 <= d < 2^16) of numerators x < 2^16 by
+// a multiply-high with m = ceil(2^32 / d); exact in that range.
+struct FastDiv {
+  int d;
+  unsigned m;
+  __host__ __device__ __forceinline__ int div(int x) const {
+#ifdef __HIP_DEVICE_COMPILE__
+    return d == 1 ? x : int(__umulhi(unsigned(x), m));
+#else
+    return x / d;
+#endif
+  }
+};
+FastDiv make_fastdiv(int d);
 
 struct FftDesc {
   int n;
   int npass;
   int radix[kMaxPass];
+  int twstep[kMaxPass];   // n / (Ls * R)
+  FastDiv ls[kMaxPass];   // Ls before the pass (product of earlier radices)
+  FastDiv nbf[kMaxPass];  // butterflies per sequence, n / R
 };
 
 // smallest even integer >= n whose only prime factors are 2, 3 and 5
