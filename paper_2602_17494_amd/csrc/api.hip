@@ -97,7 +97,7 @@ void build_subs1(SubSet& ss, int n2, int n1, hipStream_t s) {
   ss.sf.nsub = int(ss.subs.size());
   ss.sf.fr = fr;
   ss.sf.fp = align_pitch(fp);
-  ss.sf.plane = (long long)fr * fp;
+  ss.sf.plane = (long long)fr * ss.sf.fp;
   ss.sf.ay = ss.ay;
   ss.sf.ax = ss.ax;
 }
@@ -132,7 +132,7 @@ void build_subs2(SubSet& ss, int N2, int N1, hipStream_t s) {
   ss.sf.nsub = int(ss.subs.size());
   ss.sf.fr = fr;
   ss.sf.fp = align_pitch(fp);
-  ss.sf.plane = (long long)fr * fp;
+  ss.sf.plane = (long long)fr * ss.sf.fp;
   ss.sf.ay = ss.ay;
   ss.sf.ax = ss.ax;
 }
@@ -276,10 +276,10 @@ Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layou
   const size_t fpb = size_t(P->ss.sf.plane) * P->ss.sf.nsub * sizeof(T);
   P->va.alloc(4 * fpb);
   P->vb.alloc(4 * fpb);
+  P->omega.alloc(2 * fpb);
   if (!P->plain) {
     P->vt.alloc(4 * fpb);
     P->zw.alloc(2 * fpb);
-    P->omega.alloc(2 * fpb);
   }
   P->za.alloc(2 * fpb);
   P->zb.alloc(2 * fpb);
@@ -358,8 +358,9 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
   launch_fill<T>(dptr<T>(P.va), 4 * sf.plane * sf.nsub, T(0), s);
   launch_fill<T>(dptr<T>(P.vb), 4 * sf.plane * sf.nsub, T(0), s);
   GreenPlan<T>& lp = P.plain ? *P.global : *P.local;
-  // in the single-domain case the frame is the grid and omega = f
-  const T* omega = P.plain ? dptr<T>(P.f1) : dptr<T>(P.omega);
+  // in the single-domain case omega = f (theta = 1), staged into the frame layout
+  if (P.plain) launch_sub_theta_p<T>(sf, g, dptr<T>(P.f1), 2, dptr<T>(P.omega), s);
+  const T* omega = dptr<T>(P.omega);
   T* cur = dptr<T>(P.va);
   T* nxt = dptr<T>(P.vb);
   T* zcur = dptr<T>(P.za);  // vecdiv of cur (0 for v = 0)

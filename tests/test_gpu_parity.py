@@ -74,6 +74,8 @@ CASES = [
     (70, 37, (3, 2, 5, 4), 2, 3),
     (64, 64, (2, 2, 8, 8), 2, 5),
     (100, 131, (4, 4, 6, 6), 2, 2),
+    (150, 200, (2, 2, 6, 8), 2, 2),   # frames wider than 64 columns (padded pitch)
+    (90, 140, (1, 1, 0, 0), 2, 3),    # single domain, padded pitch
 ]
 
 
