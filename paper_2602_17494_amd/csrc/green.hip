@@ -315,16 +315,20 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   }
 }
 
+// Launch order: the box index is the fastest grid dimension, so consecutive
+// workgroups (dealt round-robin to the eight XCDs) work on the same column
+// tile of neighbouring boxes; boxes of one subdomain column then share an
+// XCD and its L2 for the window spectra they have in common.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   using C = cplx<T>;
   constexpr int MAXS = FftCap<T, NT>::elems;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const int b = blockIdx.y;
+  const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
   const int Li = d.Li, Lh = d.Lh, cpw = d.cpw;
-  const int k0 = blockIdx.x * cpw;
+  const int k0 = blockIdx.y * cpw;
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   for (int c = 0; c < cpw; ++c) {
     const int k = k0 + c;
@@ -421,23 +425,29 @@ static void allow_lds(F* f, size_t bytes) {
                                                  static_cast<int>(bytes)));
 }
 
-// Workgroup size and batch for transforms of length n: 256 threads when one
-// transform fits their register staging, 1024 otherwise; as many transforms
-// per workgroup as fit both the staging and `max_lds` bytes of LDS.
+// Workgroup size and batch for transforms of length n: the batch (rows or
+// columns per workgroup) sets the granularity of the row/column transpose
+// through HBM, so aim for `want` sequences per workgroup (128-byte chunks),
+// using 1024 threads when 256 cannot stage them, within `max_lds` bytes.
 struct Batch {
   int nt, batch;
 };
 template <typename T>
-static Batch pick_batch(int n, int max_batch, size_t max_lds) {
+static Batch pick_batch(int n, int want, size_t max_lds) {
   const size_t elem_bytes = sizeof(cplx<T>);
   constexpr int cs = FftCap<T, kFftThreads>::elems, cl = FftCap<T, kFftThreadsLong>::elems;
+  if (n > kFftThreadsLong * cl)
+    throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
+  const int by_lds = std::max<int>(1, int(max_lds / (size_t(n) * elem_bytes)));
+  const int target = std::max(1, std::min(want, by_lds));
   Batch b{};
-  int cap = 0;
-  if (n <= kFftThreads * cs) { b.nt = kFftThreads; cap = cs; }
-  else if (n <= kFftThreadsLong * cl) { b.nt = kFftThreadsLong; cap = cl; }
-  else throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
-  b.batch = std::min(max_batch, std::max(1, (b.nt * cap) / n));
-  while (b.batch > 1 && size_t(b.batch) * n * elem_bytes > max_lds) --b.batch;
+  if (size_t(target) * n <= size_t(kFftThreads) * cs) {
+    b.nt = kFftThreads;
+    b.batch = target;
+  } else {
+    b.nt = kFftThreadsLong;
+    b.batch = std::max(1, std::min(target, (kFftThreadsLong * cl) / n));
+  }
   if (size_t(b.batch) * n * elem_bytes > 160 * 1024)
     throw Error(-1, "FFT length " + std::to_string(n) + " does not fit in LDS");
   return b;
@@ -500,7 +510,7 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     const size_t chunk = std::max<size_t>(1, (size_t(512) << 20) / (per_slot * sizeof(cplx<double>)));
     DevBuf tmp(sizeof(cplx<double>) * std::min(chunk, nslot) * per_slot);
     const Batch br = pick_batch<double>(Lj, 8, 80 * 1024);
-    const Batch bc = pick_batch<double>(Li, 16, 80 * 1024);
+    const Batch bc = pick_batch<double>(Li, 8, 80 * 1024);
     const size_t lds_r = size_t(br.batch) * Lj * sizeof(cplx<double>);
     const size_t lds_c = size_t(bc.batch) * Li * sizeof(cplx<double>);
     auto kr = br.nt == kFftThreads ? k_spec_rows<kFftThreads> : k_spec_rows<kFftThreadsLong>;
@@ -522,8 +532,11 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     TVS_HIP(hipStreamSynchronize(s));
   }
 
+  // 8 row pairs (16 rows) per workgroup give 128-byte chunks of float32 half
+  // spectra in the transposed layout; the column pass, which is bound by
+  // its barriers rather than by HBM, keeps 256-thread workgroups
   const Batch br = pick_batch<T>(Lj, 8, 80 * 1024);
-  const Batch bc = pick_batch<T>(Li, 16, 80 * 1024);
+  const Batch bc = pick_batch<T>(Li, std::max(1, (kFftThreads * FftCap<T, kFftThreads>::elems) / Li), 80 * 1024);
   nt_rows_ = br.nt;
   nt_cols_ = bc.nt;
   dev_.n2 = n2;
@@ -583,7 +596,7 @@ void GreenPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame& p
   const size_t lds_r = size_t(dev_.ppw) * Lj * sizeof(cplx<T>);
   const size_t lds_c = size_t(dev_.cpw) * Li * sizeof(cplx<T>);
   const int row_groups = ((rows_max + 1) / 2 + dev_.ppw - 1) / dev_.ppw;
-  const dim3 gr(row_groups, nbox), gc((dev_.Lh + dev_.cpw - 1) / dev_.cpw, nbox);
+  const dim3 gr(row_groups, nbox), gc(nbox, (dev_.Lh + dev_.cpw - 1) / dev_.cpw);
   const std::string t(tag);
   KernelTimer::time(timer, (t + "_rows_fwd").c_str(), bytes_rows_fwd(), s, [&] {
     if (nt_rows_ == kFftThreads)
