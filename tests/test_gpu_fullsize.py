@@ -1,0 +1,75 @@
+"""The 2048 x 2048 workload in the launch configuration bench.py times
+(float32, 8 x 8 subdomains, 16-pixel shared stripes).
+
+* Reduced counts (2 sweeps x 2 inner): sampled outputs and row sums against
+  the FP64 oracle's values stored by tests/golden/make_golden_2048.py.
+* Full counts (20 sweeps x 500 inner), where the oracle cannot run: properties
+  that hold at any size -- the float32 image agrees with the float64 run of
+  the same kernels to 1e-4, tau is divergence free (float64), the duality
+  gaps are non-negative and the energies finite."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators as op
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_2048_s2i2.npz")
+N = 2048
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_17494_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def solve(ctx, dtype, sweeps, inner):
+    from paper_2602_17494_amd import make_iters, make_layout, make_params
+    _, d64 = synth.noisy_f32(N, N, 0.1, 31)
+    delta, alpha = synth.params_for_sigma(0.1)
+    d0 = torch.tensor(d64, dtype=dtype, device="cuda:0")
+    tau = torch.empty((2, N + 1, N + 1), dtype=dtype, device="cuda:0")
+    d, st = ctx.schwarz_solve(d0, make_params(delta, alpha), make_layout(8, 8, 16, 16),
+                              make_iters(sweeps, inner), tau_out=tau)
+    torch.cuda.synchronize()
+    return d, tau, st
+
+
+@pytest.mark.parametrize("dtype,tol_d,tol_tau", [("f64", 1e-10, 1e-10), ("f32", 1e-4, 1e-5)])
+def test_2048_reduced_counts_against_oracle(ctx, dtype, tol_d, tol_tau):
+    g = np.load(GOLDEN)
+    meta = g["meta"]
+    t = torch.float64 if dtype == "f64" else torch.float32
+    d, tau, st = solve(ctx, t, int(meta[2]), int(meta[3]))
+    d = d.double().cpu().numpy()
+    tau = tau.double().cpu().numpy()
+    ii, jj = g["ii"], g["jj"]
+    assert np.abs(tau[0, ii, jj] - g["tau1"]).max() < tol_tau
+    assert np.abs(tau[1, ii, jj] - g["tau2"]).max() < tol_tau
+    assert np.abs(d[np.minimum(ii, N - 1), np.minimum(jj, N - 1)] - g["d"]).max() < tol_d
+    # row sums cover every pixel; N terms each
+    assert np.abs(d.sum(axis=1) - g["d_rowsum"]).max() < tol_d * N
+    assert np.abs(tau[1].sum(axis=1) - g["tau2_rowsum"]).max() < tol_tau * N
+    assert st[0]["energy"] == pytest.approx(float(g["energy1"][-1]), rel=1e-9 if dtype == "f64" else 1e-5)
+    assert st[1]["energy"] == pytest.approx(float(g["energy2"][-1]), rel=1e-9 if dtype == "f64" else 1e-5)
+
+
+def test_2048_full_counts_properties(ctx):
+    d32, _, st32 = solve(ctx, torch.float32, 20, 500)
+    d64, tau64, st64 = solve(ctx, torch.float64, 20, 500)
+    err = float((d32.double() - d64).abs().max())
+    assert err < 1e-4, err
+    div = op.div(tau64.cpu().numpy())
+    assert np.abs(div).max() < 1e-10
+    for st in (st32, st64):
+        assert st[0]["gap"] >= 0 and st[1]["gap"] >= 0
+        assert np.isfinite([st[0]["energy"], st[1]["energy"]]).all()
