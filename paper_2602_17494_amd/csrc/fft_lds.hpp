@@ -1,12 +1,13 @@
-// Mixed-radix (2, 3, 4, 5) Stockham FFT held entirely in LDS.
+// Mixed-radix (2, 3, 4, 5, 8, 9) Stockham FFT held entirely in LDS.
 //
-// A workgroup of NT threads transforms `batch` independent complex
-// sequences of length n stored in LDS at buf + b * stride.  Each pass reads
-// all of its butterfly inputs into registers, synchronises, and writes the
-// outputs to their self-sorting positions (Stockham autosort), so one LDS
-// buffer suffices.  Twiddles come from a table tw[m] = exp(-2 pi i m / n)
-// kept in global memory (L1/L2 resident).  Forward transforms use the
-// exp(-...) convention and are unnormalised; the inverse uses exp(+...).
+// A workgroup of NT threads transforms `batch` independent complex sequences
+// of length n stored in LDS at buf + b * stride.  Two LDS buffers are used in
+// turn: each pass reads every butterfly's inputs from one buffer and writes
+// the outputs to their self-sorting positions (Stockham autosort) in the
+// other, with one barrier per pass; the final data may end in either buffer
+// and fft_lds returns it.  Twiddles come from a table tw[m] = exp(-2 pi i m/n)
+// in global memory (L1/L2 resident).  Forward transforms use the exp(-...)
+// convention and are unnormalised; the inverse uses exp(+...).
 #pragma once
 
 #include "tvs_internal.hpp"
@@ -16,124 +17,176 @@ namespace tvs {
 constexpr int kFftThreads = 256;       // workgroup size for short transforms
 constexpr int kFftThreadsLong = 1024;  // workgroup size for long transforms
 
-// Elements per thread the register staging can hold for one pass, kept
-// small so that several workgroups share a CU (about 100 VGPRs).  The
-// 1024-thread float variant holds a little more so that one workgroup can
-// transform sequences up to 10240 points.
+// Elements per thread per pass the engine is sized for (butterflies per
+// thread = elems / radix, rounded up).
 template <typename T, int NT> struct FftCap { static constexpr int elems = 8; };
 template <> struct FftCap<float, 1024> { static constexpr int elems = 10; };
+
+template <typename T>
+__device__ __forceinline__ void dft2(cplx<T>& a, cplx<T>& b) {
+  const cplx<T> s = cadd(a, b), d = csub(a, b);
+  a = s;
+  b = d;
+}
+
+template <typename T>
+__device__ __forceinline__ void dft3(cplx<T>& a, cplx<T>& b, cplx<T>& c, bool inv) {
+  using C = cplx<T>;
+  const T s = inv ? T(-0.86602540378443864676) : T(0.86602540378443864676);
+  const C sum = cadd(b, c), dif = csub(b, c);
+  const C mid = C{a.x - T(0.5) * sum.x, a.y - T(0.5) * sum.y};
+  const C rot = C{s * dif.y, -s * dif.x};  // -i s (b - c)
+  a = cadd(a, sum);
+  b = cadd(mid, rot);
+  c = csub(mid, rot);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cplx<T>& a, cplx<T>& b, cplx<T>& c, cplx<T>& d, bool inv) {
+  using C = cplx<T>;
+  const C s0 = cadd(a, c), d0 = csub(a, c);
+  const C s1 = cadd(b, d), d1 = csub(b, d);
+  const C mi = inv ? C{-d1.y, d1.x} : C{d1.y, -d1.x};  // (+i or -i) d1
+  a = cadd(s0, s1);
+  c = csub(s0, s1);
+  b = cadd(d0, mi);
+  d = csub(d0, mi);
+}
 
 template <int R, typename T>
 __device__ __forceinline__ void butterfly(cplx<T>* v, bool inv) {
   using C = cplx<T>;
   if constexpr (R == 2) {
-    C a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
+    dft2(v[0], v[1]);
   } else if constexpr (R == 3) {
-    const T s = inv ? T(-0.86602540378443864676) : T(0.86602540378443864676);
-    C a = v[0], b = v[1], c = v[2];
-    C sum = cadd(b, c);
-    C dif = csub(b, c);
-    C mid = C{a.x - T(0.5) * sum.x, a.y - T(0.5) * sum.y};
-    // -i * s * dif
-    C rot = C{s * dif.y, -s * dif.x};
-    v[0] = cadd(a, sum);
-    v[1] = cadd(mid, rot);
-    v[2] = csub(mid, rot);
+    dft3(v[0], v[1], v[2], inv);
   } else if constexpr (R == 4) {
-    C a = v[0], b = v[1], c = v[2], d = v[3];
-    C s0 = cadd(a, c), d0 = csub(a, c);
-    C s1 = cadd(b, d), d1 = csub(b, d);
-    // forward: y1 = d0 - i d1, y3 = d0 + i d1
-    C mi = inv ? C{-d1.y, d1.x} : C{d1.y, -d1.x};  // (-i or +i) * d1
-    v[0] = cadd(s0, s1);
-    v[2] = csub(s0, s1);
-    v[1] = cadd(d0, mi);
-    v[3] = csub(d0, mi);
+    dft4(v[0], v[1], v[2], v[3], inv);
   } else if constexpr (R == 5) {
     const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
     const T s1 = inv ? T(-0.95105651629515357212) : T(0.95105651629515357212);
     const T s2 = inv ? T(-0.58778525229247312917) : T(0.58778525229247312917);
-    C x0 = v[0];
-    C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
-    C a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
-    C r1 = C{x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
-    C r2 = C{x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
+    const C x0 = v[0];
+    const C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const C a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const C r1 = C{x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
+    const C r2 = C{x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
     // i1 = s1 b1 + s2 b2, i2 = s2 b1 - s1 b2; y = r -/+ i * i
-    C i1 = C{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};
-    C i2 = C{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};
+    const C i1 = C{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};
+    const C i2 = C{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};
     v[0] = C{x0.x + a1.x + a2.x, x0.y + a1.y + a2.y};
     v[1] = C{r1.x + i1.y, r1.y - i1.x};
     v[4] = C{r1.x - i1.y, r1.y + i1.x};
     v[2] = C{r2.x + i2.y, r2.y - i2.x};
     v[3] = C{r2.x - i2.y, r2.y + i2.x};
+  } else if constexpr (R == 8) {
+    // 4-point DFTs of the even and odd inputs, twiddles w8^k, then 2-point
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3, inv);
+    dft4(o0, o1, o2, o3, inv);
+    const T h = T(0.70710678118654752440);
+    // forward w8 = (1 - i)/sqrt2, w8^2 = -i, w8^3 = (-1 - i)/sqrt2; the inverse conjugates
+    const C t1 = inv ? C{h * (o1.x - o1.y), h * (o1.x + o1.y)} : C{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+    const C t2 = inv ? C{-o2.y, o2.x} : C{o2.y, -o2.x};
+    const C t3 = inv ? C{-h * (o3.x + o3.y), h * (o3.x - o3.y)} : C{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1);
+    v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2);
+    v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3);
+    v[7] = csub(e3, t3);
+  } else if constexpr (R == 9) {
+    // 3-point DFTs of the stride-3 inputs, twiddles w9^(l k), then 3-point
+    C y[3][3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      y[l][0] = v[l];
+      y[l][1] = v[3 + l];
+      y[l][2] = v[6 + l];
+      dft3(y[l][0], y[l][1], y[l][2], inv);
+    }
+    // w9^1, w9^2, w9^4 (forward: exp(-2 pi i e / 9)); the inverse conjugates
+    const T c1 = T(0.76604444311897803520), s1v = T(0.64278760968653932632);
+    const T c2 = T(0.17364817766693034885), s2v = T(0.98480775301220805936);
+    const T c4 = T(-0.93969262078590838405), s4v = T(0.34202014332566873304);
+    const T sg = inv ? T(1) : T(-1);
+    const C w1 = C{c1, sg * s1v}, w2 = C{c2, sg * s2v}, w4 = C{c4, sg * s4v};
+    y[1][1] = cmul(y[1][1], w1);
+    y[1][2] = cmul(y[1][2], w2);
+    y[2][1] = cmul(y[2][1], w2);
+    y[2][2] = cmul(y[2][2], w4);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      C a = y[0][k], b = y[1][k], c = y[2][k];
+      dft3(a, b, c, inv);
+      v[k] = a;
+      v[k + 3] = b;
+      v[k + 6] = c;
+    }
   }
 }
 
 template <typename T, int NT, int R>
-__device__ __forceinline__ void fft_pass(cplx<T>* buf, int stride, int batch, FastDiv fls,
-                                         FastDiv fnbf, int twstep, const cplx<T>* __restrict__ tw,
-                                         bool inv) {
+__device__ __forceinline__ void fft_pass(const cplx<T>* src, cplx<T>* dst, int stride, int batch,
+                                         FastDiv fls, FastDiv fnbf, int twstep,
+                                         const cplx<T>* __restrict__ tw, bool inv) {
   using C = cplx<T>;
-  constexpr int MAXB = (FftCap<T, NT>::elems + R - 1) / R;
   const int nbf = fnbf.d, Ls = fls.d;
   const int total = nbf * batch;
-  C v[MAXB][R];
+  for (int jj = threadIdx.x; jj < total; jj += NT) {
+    const int b = fnbf.div(jj);
+    const int j = jj - b * nbf;
+    const int g = fls.div(j);
+    const int k = j - g * Ls;
+    const C* x = src + b * stride;
+    C v[R];
 #pragma unroll
-  for (int s = 0; s < MAXB; ++s) {
-    const int jj = threadIdx.x + s * NT;
-    if (jj < total) {
-      const int b = fnbf.div(jj);
-      const int j = jj - b * nbf;
-      const C* x = buf + b * stride;
-      const int k = j - fls.div(j) * Ls;
-#pragma unroll
-      for (int t = 0; t < R; ++t) {
-        C c = x[j + t * nbf];
-        if (t > 0) {
-          C w = tw[k * t * twstep];
-          if (inv) w.y = -w.y;
-          c = cmul(c, w);
-        }
-        v[s][t] = c;
+    for (int t = 0; t < R; ++t) {
+      C c = x[j + t * nbf];
+      if (t > 0) {
+        C w = tw[k * t * twstep];
+        if (inv) w.y = -w.y;
+        c = cmul(c, w);
       }
-      butterfly<R, T>(v[s], inv);
+      v[t] = c;
     }
-  }
-  __syncthreads();
+    butterfly<R, T>(v, inv);
+    C* y = dst + b * stride;
+    const int base = g * Ls * R + k;
 #pragma unroll
-  for (int s = 0; s < MAXB; ++s) {
-    const int jj = threadIdx.x + s * NT;
-    if (jj < total) {
-      const int b = fnbf.div(jj);
-      const int j = jj - b * nbf;
-      C* y = buf + b * stride;
-      const int g = fls.div(j);
-      const int k = j - g * Ls;
-      const int base = g * Ls * R + k;
-#pragma unroll
-      for (int t = 0; t < R; ++t) y[base + t * Ls] = v[s][t];
-    }
+    for (int t = 0; t < R; ++t) y[base + t * Ls] = v[t];
   }
-  __syncthreads();
 }
 
-// Transform `batch` sequences of length d.n in LDS (sequence b at
-// buf + b * stride).  Requires batch * d.n <= NT * FftCap<T, NT>::elems.
+// Transform `batch` sequences of length d.n held in buffer a (sequence b at
+// a + b * stride), using bbuf as the second buffer; returns the buffer that
+// holds the result.  The caller's writes to a must be complete (barrier)
+// before the call; the call ends with a barrier.
 template <typename T, int NT>
-__device__ void fft_lds(cplx<T>* buf, const FftDesc& d, int stride, int batch,
-                        const cplx<T>* __restrict__ tw, bool inv) {
+__device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* bbuf, const FftDesc& d, int stride, int batch,
+                            const cplx<T>* __restrict__ tw, bool inv) {
+  cplx<T>* src = a;
+  cplx<T>* dst = bbuf;
   for (int p = 0; p < d.npass; ++p) {
     const FastDiv ls = d.ls[p], nb = d.nbf[p];
     const int ts = d.twstep[p];
     switch (d.radix[p]) {
-      case 4: fft_pass<T, NT, 4>(buf, stride, batch, ls, nb, ts, tw, inv); break;
-      case 2: fft_pass<T, NT, 2>(buf, stride, batch, ls, nb, ts, tw, inv); break;
-      case 3: fft_pass<T, NT, 3>(buf, stride, batch, ls, nb, ts, tw, inv); break;
-      default: fft_pass<T, NT, 5>(buf, stride, batch, ls, nb, ts, tw, inv); break;
+      case 8: fft_pass<T, NT, 8>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
+      case 9: fft_pass<T, NT, 9>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
+      case 4: fft_pass<T, NT, 4>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
+      case 2: fft_pass<T, NT, 2>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
+      case 3: fft_pass<T, NT, 3>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
+      default: fft_pass<T, NT, 5>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
     }
+    __syncthreads();
+    cplx<T>* t = src;
+    src = dst;
+    dst = t;
   }
+  return src;
 }
 
 }  // namespace tvs

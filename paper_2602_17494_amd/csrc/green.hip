@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace tvs {
 
@@ -39,8 +40,10 @@ FftDesc make_fft_desc(int n) {
     d.radix[k++] = r;
     m /= r;
   };
+  while (m % 8 == 0) push(8);
   while (m % 4 == 0) push(4);
   while (m % 2 == 0) push(2);
+  while (m % 9 == 0) push(9);
   while (m % 3 == 0) push(3);
   while (m % 5 == 0) push(5);
   if (m != 1) throw Error(-1, "FFT length " + std::to_string(n) + " is not 2^a 3^b 5^c");
@@ -210,12 +213,12 @@ __global__ __launch_bounds__(NT) void k_spec_rows(const double* __restrict__ g, 
     buf[qq * Lj + c] = cplx<double>{va, vb};
   }
   __syncthreads();
-  fft_lds<double, NT>(buf, fj, Lj, ppw, twj, false);
+  const cplx<double>* res = fft_lds<double, NT>(buf, buf + ppw * Lj, fj, Lj, ppw, twj, false);
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int qq = e / Lh, k = e - qq * Lh;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
-    const cplx<double> z = buf[qq * Lj + k];
-    const cplx<double> zn = buf[qq * Lj + (k == 0 ? 0 : Lj - k)];
+    const cplx<double> z = res[qq * Lj + k];
+    const cplx<double> zn = res[qq * Lj + (k == 0 ? 0 : Lj - k)];
     const size_t base = static_cast<size_t>(slot) * Li * Lh;
     if (ra < Li) out[base + static_cast<size_t>(ra) * Lh + k] = cplx<double>{0.5 * (z.x + zn.x), 0.5 * (z.y - zn.y)};
     if (rb < Li) out[base + static_cast<size_t>(rb) * Lh + k] = cplx<double>{0.5 * (z.y + zn.y), 0.5 * (zn.x - z.x)};
@@ -244,13 +247,13 @@ __global__ __launch_bounds__(NT) void k_spec_cols(const cplx<double>* __restrict
     buf[c * Li + r] = (k < Lh) ? in[base + static_cast<size_t>(r) * Lh + k] : cplx<double>{0.0, 0.0};
   }
   __syncthreads();
-  fft_lds<double, NT>(buf, fi, Li, cpw, twi, false);
+  const cplx<double>* res = fft_lds<double, NT>(buf, buf + cpw * Li, fi, Li, cpw, twi, false);
   const double scale = 1.0 / (double(Li) * double(Lj));
   for (int e = threadIdx.x; e < cpw * Li; e += NT) {
     const int c = e / Li, r = e - c * Li;
     const int k = k0 + c;
     if (k >= Lh) continue;
-    cplx<double> v = buf[c * Li + r];
+    cplx<double> v = res[c * Li + r];
     v.x *= scale;
     v.y *= scale;
     if (key.z >= 0) v = cmul(v, twi[(static_cast<long long>(r) * key.z) % Li]);
@@ -280,7 +283,22 @@ __device__ __forceinline__ T div_at(const T* __restrict__ u, const Frame& f, int
   return ((a - am) + (c - cm)) * inv_h;
 }
 
-template <typename T, int NT>
+// LDS of an apply kernel: two transform buffers of batch * n elements, then
+// (TWL) the twiddle table of the transform length, which the passes gather
+// from at scattered offsets; from LDS those gathers do not queue behind the
+// vector L1.
+template <typename T, int NT, bool TWL>
+__device__ __forceinline__ const cplx<T>* stage_twiddles(cplx<T>* lds, const cplx<T>* __restrict__ tw,
+                                                         int n) {
+  if constexpr (TWL) {
+    for (int i = threadIdx.x; i < n; i += NT) lds[i] = tw[i];
+    return lds;
+  } else {
+    return tw;
+  }
+}
+
+template <typename T, int NT, bool TWL>
 __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
                                                        Frame uf) {
   using C = cplx<T>;
@@ -291,6 +309,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
+  const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * ppw * Lj, d.tw_j, Lj);
   for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
     const int qq = d.fd_Lj.div(e), c = e - qq * Lj;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
@@ -302,13 +321,13 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
     buf[qq * Lj + c] = C{va, vb};
   }
   __syncthreads();
-  fft_lds<T, NT>(buf, d.fj, Lj, ppw, d.tw_j, false);
+  const C* res = fft_lds<T, NT>(buf, buf + ppw * Lj, d.fj, Lj, ppw, tw, false);
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int k = d.fd_ppw.div(e), qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
-    const C z = buf[qq * Lj + k];
-    const C zn = buf[qq * Lj + (k == 0 ? 0 : Lj - k)];
+    const C z = res[qq * Lj + k];
+    const C zn = res[qq * Lj + (k == 0 ? 0 : Lj - k)];
     C* col = S + static_cast<size_t>(k) * d.rows_max;
     if (ra < bx.ni) col[ra] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
     if (rb < bx.ni) col[rb] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
@@ -319,68 +338,59 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
 // workgroups (dealt round-robin to the eight XCDs) work on the same column
 // tile of neighbouring boxes; boxes of one subdomain column then share an
 // XCD and its L2 for the window spectra they have in common.
-template <typename T, int NT>
+template <typename T, int NT, bool TWL>
 __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   using C = cplx<T>;
-  constexpr int MAXS = FftCap<T, NT>::elems;
   extern __shared__ unsigned char smem_raw[];
-  C* buf = reinterpret_cast<C*>(smem_raw);
+  C* bufa = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
   const int Li = d.Li, Lh = d.Lh, cpw = d.cpw;
+  C* bufb = bufa + cpw * Li;
   const int k0 = blockIdx.y * cpw;
+  const C* tw = stage_twiddles<T, NT, TWL>(bufa + 2 * cpw * Li, d.tw_i, Li);
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   for (int c = 0; c < cpw; ++c) {
     const int k = k0 + c;
     const C* col = S + static_cast<size_t>(k) * d.rows_max;
     for (int r = threadIdx.x; r < Li; r += NT)
-      buf[c * Li + r] = (r < bx.ni && k < Lh) ? col[r] : C{T(0), T(0)};
+      bufa[c * Li + r] = (r < bx.ni && k < Lh) ? col[r] : C{T(0), T(0)};
   }
   __syncthreads();
-  fft_lds<T, NT>(buf, d.fi, Li, cpw, d.tw_i, false);
+  const C* X = fft_lds<T, NT>(bufa, bufb, d.fi, Li, cpw, tw, false);
+  C* Y = (X == bufa) ? bufb : bufa;
   // Phi = X K00 + conj(X(-ki)) K01 + X(-ki) K10 + conj(X) K11
   const size_t slot_sz = static_cast<size_t>(Li) * Lh;
   const C* s00 = d.spec + static_cast<size_t>(bx.k00) * slot_sz;
   const C* s01 = d.spec + static_cast<size_t>(bx.k01) * slot_sz;
   const C* s10 = d.spec + static_cast<size_t>(bx.k10) * slot_sz;
   const C* s11 = d.spec + static_cast<size_t>(bx.k11) * slot_sz;
-  C res[MAXS];
-#pragma unroll
-  for (int s = 0; s < MAXS; ++s) {
-    const int e = threadIdx.x + s * NT;
-    if (e < cpw * Li) {
-      const int c = d.fd_Li.div(e), ki = e - c * Li;
-      const int k = k0 + c;
-      const C x = buf[c * Li + ki];
-      const C xn = buf[c * Li + (ki == 0 ? 0 : Li - ki)];
-      C acc{T(0), T(0)};
-      if (k < Lh) {
-        const size_t o = static_cast<size_t>(k) * Li + ki;
-        acc = cmul(x, s00[o]);
-        acc = cadd(acc, cmul(cconj(xn), s01[o]));
-        acc = cadd(acc, cmul(xn, s10[o]));
-        acc = cadd(acc, cmul(cconj(x), s11[o]));
-      }
-      res[s] = acc;
+  for (int c = 0; c < cpw; ++c) {
+    const int k = k0 + c;
+    if (k >= Lh) break;
+    const size_t o0 = static_cast<size_t>(k) * Li;
+    for (int ki = threadIdx.x; ki < Li; ki += NT) {
+      const C x = X[c * Li + ki];
+      const C xn = X[c * Li + (ki == 0 ? 0 : Li - ki)];
+      const size_t o = o0 + ki;
+      C acc = cmul(x, s00[o]);
+      acc = cadd(acc, cmul(cconj(xn), s01[o]));
+      acc = cadd(acc, cmul(xn, s10[o]));
+      acc = cadd(acc, cmul(cconj(x), s11[o]));
+      Y[c * Li + ki] = acc;
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int s = 0; s < MAXS; ++s) {
-    const int e = threadIdx.x + s * NT;
-    if (e < cpw * Li) buf[e] = res[s];
-  }
-  __syncthreads();
-  fft_lds<T, NT>(buf, d.fi, Li, cpw, d.tw_i, true);
+  const C* Z = fft_lds<T, NT>(Y, const_cast<C*>(X), d.fi, Li, cpw, tw, true);
   for (int c = 0; c < cpw; ++c) {
     const int k = k0 + c;
     if (k >= Lh) break;
     C* col = S + static_cast<size_t>(k) * d.rows_max;
-    for (int r = threadIdx.x; r < bx.ni; r += NT) col[r] = buf[c * Li + r];
+    for (int r = threadIdx.x; r < bx.ni; r += NT) col[r] = Z[c * Li + r];
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool TWL>
 __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restrict__ phi, Frame pf) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
@@ -390,6 +400,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;
+  const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * ppw * Lj, d.tw_j, Lj);
   const C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   const int half = Lj / 2;
   for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
@@ -402,13 +413,13 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
     buf[qq * Lj + k] = k <= half ? C{a.x - c.y, a.y + c.x} : C{a.x + c.y, c.x - a.y};
   }
   __syncthreads();
-  fft_lds<T, NT>(buf, d.fj, Lj, ppw, d.tw_j, true);
+  const C* res = fft_lds<T, NT>(buf, buf + ppw * Lj, d.fj, Lj, ppw, tw, true);
   T* out = phi + b * pf.box_stride;
   for (int qq = 0; qq < ppw; ++qq) {
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     if (ra >= bx.ni) break;
     for (int c = threadIdx.x; c < bx.nj; c += NT) {
-      const C z = buf[qq * Lj + c];
+      const C z = res[qq * Lj + c];
       out[static_cast<long long>(ra) * pf.pitch + c] = z.x;
       if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
     }
@@ -438,7 +449,7 @@ static Batch pick_batch(int n, int want, size_t max_lds) {
   constexpr int cs = FftCap<T, kFftThreads>::elems, cl = FftCap<T, kFftThreadsLong>::elems;
   if (n > kFftThreadsLong * cl)
     throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
-  const int by_lds = std::max<int>(1, int(max_lds / (size_t(n) * elem_bytes)));
+  const int by_lds = std::max<int>(1, int(max_lds / (2 * size_t(n) * elem_bytes)));
   const int target = std::max(1, std::min(want, by_lds));
   Batch b{};
   if (size_t(target) * n <= size_t(kFftThreads) * cs) {
@@ -448,7 +459,7 @@ static Batch pick_batch(int n, int want, size_t max_lds) {
     b.nt = kFftThreadsLong;
     b.batch = std::max(1, std::min(target, (kFftThreadsLong * cl) / n));
   }
-  if (size_t(b.batch) * n * elem_bytes > 160 * 1024)
+  if (2 * size_t(b.batch) * n * elem_bytes > 160 * 1024)
     throw Error(-1, "FFT length " + std::to_string(n) + " does not fit in LDS");
   return b;
 }
@@ -511,8 +522,8 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     DevBuf tmp(sizeof(cplx<double>) * std::min(chunk, nslot) * per_slot);
     const Batch br = pick_batch<double>(Lj, 8, 80 * 1024);
     const Batch bc = pick_batch<double>(Li, 8, 80 * 1024);
-    const size_t lds_r = size_t(br.batch) * Lj * sizeof(cplx<double>);
-    const size_t lds_c = size_t(bc.batch) * Li * sizeof(cplx<double>);
+    const size_t lds_r = 2 * size_t(br.batch) * Lj * sizeof(cplx<double>);
+    const size_t lds_c = 2 * size_t(bc.batch) * Li * sizeof(cplx<double>);
     auto kr = br.nt == kFftThreads ? k_spec_rows<kFftThreads> : k_spec_rows<kFftThreadsLong>;
     auto kc = bc.nt == kFftThreads ? k_spec_cols<T, kFftThreads> : k_spec_cols<T, kFftThreadsLong>;
     allow_lds(kr, lds_r);
@@ -558,14 +569,60 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   dev_.spec = spec_.as<cplx<T>>();
   dev_.fi = fi;
   dev_.fj = fj;
-  const size_t lds_r = size_t(dev_.ppw) * Lj * sizeof(cplx<T>);
-  const size_t lds_c = size_t(dev_.cpw) * Li * sizeof(cplx<T>);
-  allow_lds(k_green_rows_fwd<T, kFftThreads>, lds_r);
-  allow_lds(k_green_rows_fwd<T, kFftThreadsLong>, lds_r);
-  allow_lds(k_green_rows_inv<T, kFftThreads>, lds_r);
-  allow_lds(k_green_rows_inv<T, kFftThreadsLong>, lds_r);
-  allow_lds(k_green_cols<T, kFftThreads>, lds_c);
-  allow_lds(k_green_cols<T, kFftThreadsLong>, lds_c);
+  twl_rows_ = Lj * sizeof(cplx<T>) <= 16 * 1024;
+  twl_cols_ = Li * sizeof(cplx<T>) <= 16 * 1024;
+  for_each_variant([&](auto rf, auto cf, auto ri) {
+    allow_lds(rf, lds_rows());
+    allow_lds(ri, lds_rows());
+    allow_lds(cf, lds_cols());
+  });
+}
+
+template <typename T>
+size_t GreenPlan<T>::lds_rows() const {
+  return (2 * size_t(dev_.ppw) + (twl_rows_ ? 1 : 0)) * Lj * sizeof(cplx<T>);
+}
+template <typename T>
+size_t GreenPlan<T>::lds_cols() const {
+  return (2 * size_t(dev_.cpw) + (twl_cols_ ? 1 : 0)) * Li * sizeof(cplx<T>);
+}
+
+// Calls f(rows_fwd, cols, rows_inv) with the kernel instantiations this plan
+// launches (workgroup size and twiddle placement of each pass).
+template <typename T>
+template <typename F>
+void GreenPlan<T>::for_each_variant(F&& f) const {
+  auto pick = [&](auto nt_r, auto nt_c, auto twr, auto twc) {
+    f(k_green_rows_fwd<T, decltype(nt_r)::value, decltype(twr)::value>,
+      k_green_cols<T, decltype(nt_c)::value, decltype(twc)::value>,
+      k_green_rows_inv<T, decltype(nt_r)::value, decltype(twr)::value>);
+  };
+  using S = std::integral_constant<int, kFftThreads>;
+  using L = std::integral_constant<int, kFftThreadsLong>;
+  using Y = std::true_type;
+  using N = std::false_type;
+  const bool rs = nt_rows_ == kFftThreads, cs = nt_cols_ == kFftThreads;
+  if (rs && cs) {
+    if (twl_rows_ && twl_cols_) pick(S{}, S{}, Y{}, Y{});
+    else if (twl_rows_) pick(S{}, S{}, Y{}, N{});
+    else if (twl_cols_) pick(S{}, S{}, N{}, Y{});
+    else pick(S{}, S{}, N{}, N{});
+  } else if (rs) {
+    if (twl_rows_ && twl_cols_) pick(S{}, L{}, Y{}, Y{});
+    else if (twl_rows_) pick(S{}, L{}, Y{}, N{});
+    else if (twl_cols_) pick(S{}, L{}, N{}, Y{});
+    else pick(S{}, L{}, N{}, N{});
+  } else if (cs) {
+    if (twl_rows_ && twl_cols_) pick(L{}, S{}, Y{}, Y{});
+    else if (twl_rows_) pick(L{}, S{}, Y{}, N{});
+    else if (twl_cols_) pick(L{}, S{}, N{}, Y{});
+    else pick(L{}, S{}, N{}, N{});
+  } else {
+    if (twl_rows_ && twl_cols_) pick(L{}, L{}, Y{}, Y{});
+    else if (twl_rows_) pick(L{}, L{}, Y{}, N{});
+    else if (twl_cols_) pick(L{}, L{}, N{}, Y{});
+    else pick(L{}, L{}, N{}, N{});
+  }
 }
 
 template <typename T>
@@ -593,31 +650,23 @@ double GreenPlan<T>::bytes_rows_inv() const {
 template <typename T>
 void GreenPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t s,
                              KernelTimer* timer, const char* tag) {
-  const size_t lds_r = size_t(dev_.ppw) * Lj * sizeof(cplx<T>);
-  const size_t lds_c = size_t(dev_.cpw) * Li * sizeof(cplx<T>);
   const int row_groups = ((rows_max + 1) / 2 + dev_.ppw - 1) / dev_.ppw;
   const dim3 gr(row_groups, nbox), gc(nbox, (dev_.Lh + dev_.cpw - 1) / dev_.cpw);
+  const size_t lr = lds_rows(), lc = lds_cols();
   const std::string t(tag);
-  KernelTimer::time(timer, (t + "_rows_fwd").c_str(), bytes_rows_fwd(), s, [&] {
-    if (nt_rows_ == kFftThreads)
-      hipLaunchKernelGGL((k_green_rows_fwd<T, kFftThreads>), gr, dim3(kFftThreads), lds_r, s, dev_, u, uf);
-    else
-      hipLaunchKernelGGL((k_green_rows_fwd<T, kFftThreadsLong>), gr, dim3(kFftThreadsLong), lds_r, s, dev_, u, uf);
-    TVS_LAUNCH_CHECK();
-  });
-  KernelTimer::time(timer, (t + "_cols").c_str(), bytes_cols(), s, [&] {
-    if (nt_cols_ == kFftThreads)
-      hipLaunchKernelGGL((k_green_cols<T, kFftThreads>), gc, dim3(kFftThreads), lds_c, s, dev_);
-    else
-      hipLaunchKernelGGL((k_green_cols<T, kFftThreadsLong>), gc, dim3(kFftThreadsLong), lds_c, s, dev_);
-    TVS_LAUNCH_CHECK();
-  });
-  KernelTimer::time(timer, (t + "_rows_inv").c_str(), bytes_rows_inv(), s, [&] {
-    if (nt_rows_ == kFftThreads)
-      hipLaunchKernelGGL((k_green_rows_inv<T, kFftThreads>), gr, dim3(kFftThreads), lds_r, s, dev_, phi, pf);
-    else
-      hipLaunchKernelGGL((k_green_rows_inv<T, kFftThreadsLong>), gr, dim3(kFftThreadsLong), lds_r, s, dev_, phi, pf);
-    TVS_LAUNCH_CHECK();
+  for_each_variant([&](auto rf, auto cf, auto ri) {
+    KernelTimer::time(timer, (t + "_rows_fwd").c_str(), bytes_rows_fwd(), s, [&] {
+      hipLaunchKernelGGL(rf, gr, dim3(nt_rows_), lr, s, dev_, u, uf);
+      TVS_LAUNCH_CHECK();
+    });
+    KernelTimer::time(timer, (t + "_cols").c_str(), bytes_cols(), s, [&] {
+      hipLaunchKernelGGL(cf, gc, dim3(nt_cols_), lc, s, dev_);
+      TVS_LAUNCH_CHECK();
+    });
+    KernelTimer::time(timer, (t + "_rows_inv").c_str(), bytes_rows_inv(), s, [&] {
+      hipLaunchKernelGGL(ri, gr, dim3(nt_rows_), lr, s, dev_, phi, pf);
+      TVS_LAUNCH_CHECK();
+    });
   });
 }
 

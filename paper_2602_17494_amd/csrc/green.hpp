@@ -89,6 +89,9 @@ class GreenPlan {
  private:
   GreenDev<T> dev_{};
   int nt_rows_ = 0, nt_cols_ = 0;
+  bool twl_rows_ = false, twl_cols_ = false;  // twiddle tables staged in LDS
+  size_t lds_rows() const, lds_cols() const;
+  template <typename F> void for_each_variant(F&& f) const;
   double sum_ni_lh_ = 0, sum_box_px_ = 0;
   DevBuf boxes_d_, tw_i_, tw_j_, spec_, S_;
 };
