@@ -62,10 +62,39 @@ using ProbKey = std::tuple<int, int, double, int, int, int, int>;  // N2, N1, h,
 struct SubSet {
   AxisLayout ay{}, ax{};
   std::vector<SubDesc> subs;
-  DevBuf subs_d;
+  DevBuf subs_d, theta_d;
   SubFrames sf{};
   double sub_px = 0;  // sum of subdomain sizes (points)
 };
+
+// theta tables of the frames: row r of subdomain row m2 is grid row
+// ay.start[m2] + r (0 beyond the subdomain), and likewise for columns
+void build_theta_tables(SubSet& ss, hipStream_t s) {
+  const int fr = ss.sf.fr, fp = ss.sf.fp, m2 = ss.ay.m, m1 = ss.ax.m;
+  const size_t ny = size_t(m2) * fr, nx = size_t(m1) * fp;
+  std::vector<double> td(ny + nx);
+  std::vector<float> tf(ny + nx);
+  for (int a = 0; a < m2; ++a)
+    for (int r = 0; r < fr; ++r) {
+      td[size_t(a) * fr + r] = axis_theta<double>(ss.ay, a, ss.ay.start[a] + r);
+      tf[size_t(a) * fr + r] = axis_theta<float>(ss.ay, a, ss.ay.start[a] + r);
+    }
+  for (int b = 0; b < m1; ++b)
+    for (int q = 0; q < fp; ++q) {
+      td[ny + size_t(b) * fp + q] = axis_theta<double>(ss.ax, b, ss.ax.start[b] + q);
+      tf[ny + size_t(b) * fp + q] = axis_theta<float>(ss.ax, b, ss.ax.start[b] + q);
+    }
+  const size_t bd = td.size() * sizeof(double);
+  ss.theta_d.alloc(bd + tf.size() * sizeof(float));
+  char* base = static_cast<char*>(ss.theta_d.p);
+  TVS_HIP(hipMemcpyAsync(base, td.data(), bd, hipMemcpyHostToDevice, s));
+  TVS_HIP(hipMemcpyAsync(base + bd, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  TVS_HIP(hipStreamSynchronize(s));
+  ss.sf.thy_d = reinterpret_cast<const double*>(base);
+  ss.sf.thx_d = ss.sf.thy_d + ny;
+  ss.sf.thy_f = reinterpret_cast<const float*>(base + bd);
+  ss.sf.thx_f = ss.sf.thy_f + ny;
+}
 
 // Step 1 subdomains on Omega-tilde: s = the subdomain, a = grown by one
 // row/column, b = grown by two (clipped at the grid)
@@ -98,8 +127,11 @@ void build_subs1(SubSet& ss, int n2, int n1, hipStream_t s) {
   ss.sf.fr = fr;
   ss.sf.fp = align_pitch(fp);
   ss.sf.plane = (long long)fr * ss.sf.fp;
+  // byte offsets inside one subdomain's four planes are 32-bit in the kernels
+  if (4 * 8 * ss.sf.plane >= (1LL << 32)) throw Error(TVS_EINVAL, "layout: subdomain frame too large");
   ss.sf.ay = ss.ay;
   ss.sf.ax = ss.ax;
+  build_theta_tables(ss, s);
 }
 
 // Step 2 subdomains: the Step-1 ones cut to Omega; a = grown by one
@@ -133,8 +165,11 @@ void build_subs2(SubSet& ss, int N2, int N1, hipStream_t s) {
   ss.sf.fr = fr;
   ss.sf.fp = align_pitch(fp);
   ss.sf.plane = (long long)fr * ss.sf.fp;
+  // byte offsets inside one subdomain's four planes are 32-bit in the kernels
+  if (4 * 8 * ss.sf.plane >= (1LL << 32)) throw Error(TVS_EINVAL, "layout: subdomain frame too large");
   ss.sf.ay = ss.ay;
   ss.sf.ax = ss.ax;
+  build_theta_tables(ss, s);
 }
 
 template <typename T>

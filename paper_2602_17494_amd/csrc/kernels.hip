@@ -310,46 +310,112 @@ void launch_sub_omega(const SubFrames& sf, Grid g, T inv_h, const T* r, const T*
   TVS_LAUNCH_CHECK();
 }
 
+// Element e of an array given by a 32-bit element offset (so the address is a
+// scalar base plus a 32-bit vector offset).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, unsigned e) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * unsigned(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, unsigned e, T x) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * unsigned(sizeof(T))) = x;
+}
+
+// theta / (theta + t sqrt(nn)): FP32 uses the hardware square root (about
+// 1 ulp) and the hardware reciprocal refined by one Newton step; FP64 the
+// correctly rounded operations.
+__device__ __forceinline__ float dual_scale(float th, float t, float nn) {
+  const float d = th + t * __builtin_amdgcn_sqrtf(nn);
+  float r = __builtin_amdgcn_rcpf(d);
+  r = fmaf(r, fmaf(-d, r, 1.0f), r);
+  return th * r;
+}
+__device__ __forceinline__ double dual_scale(double th, double t, double nn) {
+  return th / (th + t * sqrt(nn));
+}
+
 // Inner iteration of Algorithm 5:
 //   y = LP_m(z) = z - grad phi,  psi_k = grad(y_k - omega_k) on the subdomain,
 //   v_k <- theta (v_k + t psi_k) / (theta + t |psi_k|).
+// Each thread walks kRunY consecutive rows of one column; w_k = y_k - omega_k
+// at (r + 1, q), needed for psi at row r, is carried to the next row.  The
+// wavefront spans one row segment (kBX == 64), so row quantities are uniform.
+// Neighbour offsets are clamped to 0 where the grid ends, which makes the
+// corresponding forward difference of phi vanish and keeps every load inside
+// the frame; psi components there are set to 0 explicitly.
+constexpr int kRunY = 8;
+
+static dim3 grid_runs(int n2, int n1, int nz) {
+  return dim3((n1 + kBX - 1) / kBX, (n2 + kBY * kRunY - 1) / (kBY * kRunY), nz);
+}
+
 template <typename T>
-__global__ void k_sub_update1(SubFrames sf, Grid g, StepScalars<T> cs, const T* __restrict__ v,
-                              const T* __restrict__ z, const T* __restrict__ phi,
-                              const T* __restrict__ omega, T* __restrict__ v_out) {
-  const int q = blockIdx.x * kBX + threadIdx.x, r = blockIdx.y * kBY + threadIdx.y;
+__global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, Grid g, StepScalars<T> cs,
+                                                         const T* __restrict__ v,
+                                                         const T* __restrict__ z,
+                                                         const T* __restrict__ phi,
+                                                         const T* __restrict__ omega,
+                                                         T* __restrict__ v_out) {
+  const int q = blockIdx.x * kBX + threadIdx.x;
+  const int r0 = __builtin_amdgcn_readfirstlane((blockIdx.y * kBY + threadIdx.y) * kRunY);
   const SubDesc sd = sf.subs[blockIdx.z];
-  if (r >= sd.si || q >= sd.sj) return;
-  const long long lo = (long long)r * sf.fp + q;
-  const T* vb = v + (long long)blockIdx.z * 4 * sf.plane;
-  T* vo = v_out + (long long)blockIdx.z * 4 * sf.plane;
-  const T* zb = z + (long long)blockIdx.z * 2 * sf.plane;
-  const T* pb = phi + (long long)blockIdx.z * sf.plane;
-  const T* ob = omega + (long long)blockIdx.z * 2 * sf.plane;
-  const int gi = sd.i0 + r, gj = sd.j0 + q;
-  const bool lastx = gj == g.n1 - 1, lasty = gi == g.n2 - 1;
-  const T th = theta_at<T>(sf, sd, gi, gj);
-  for (int k = 0; k < 2; ++k) {
-    const T* zk = zb + k * sf.plane;
-    const T* ok = ob + k * sf.plane;
-    // w = y_k - omega_k at (r, q), (r, q+1), (r+1, q)
-    auto w_at = [&](long long o, int ggi, int ggj) {
-      return zk[o] - dp_frame(pb, o, sf.fp, ggi, ggj, g, k, cs.inv_h) - ok[o];
-    };
-    const T w0 = w_at(lo, gi, gj);
-    const T px = lastx ? T(0) : (w_at(lo + 1, gi, gj + 1) - w0) * cs.inv_h;
-    const T py = lasty ? T(0) : (w_at(lo + sf.fp, gi + 1, gj) - w0) * cs.inv_h;
-    const T nrm = sqrt(px * px + py * py);
-    const T den = th + cs.t * nrm;
-    const T vx = vb[(2 * k) * sf.plane + lo], vy = vb[(2 * k + 1) * sf.plane + lo];
-    vo[(2 * k) * sf.plane + lo] = th * (vx + cs.t * px) / den;
-    vo[(2 * k + 1) * sf.plane + lo] = th * (vy + cs.t * py) / den;
+  if (r0 >= sd.si || q >= sd.sj) return;
+  const unsigned fp = sf.fp, pl = unsigned(sf.plane);
+  const size_t box = blockIdx.z;
+  const T* v0 = v + box * 4 * pl;
+  const T* v1 = v0 + pl;
+  const T* v2 = v1 + pl;
+  const T* v3 = v2 + pl;
+  T* o0 = v_out + box * 4 * pl;
+  T* o1 = o0 + pl;
+  T* o2 = o1 + pl;
+  T* o3 = o2 + pl;
+  const T* z0 = z + box * 2 * pl;
+  const T* z1 = z0 + pl;
+  const T* m0 = omega + box * 2 * pl;
+  const T* m1 = m0 + pl;
+  const T* ph = phi + box * pl;
+  const T* thy = theta_rows<T>(sf) + sd.m2 * sf.fr;
+  const T ih = cs.inv_h, t = cs.t;
+  const int gj = sd.j0 + q;
+  const bool lastx = gj == g.n1 - 1;                   // psi_x = 0, (grad phi)_x = 0
+  const unsigned dx = lastx ? 0u : 1u;                  // (grad phi)_x at column q
+  const unsigned de = lastx ? 0u : 1u;                  // right neighbour
+  const unsigned dxe = (lastx || gj + 1 == g.n1 - 1) ? 0u : 1u;  // (grad phi)_x there
+  const T thx = theta_cols<T>(sf)[sd.m1 * sf.fp + q];
+  unsigned o = unsigned(r0) * fp + unsigned(q);
+  int gi = sd.i0 + r0;
+  T wa0 = ld32(z0, o) - (ld32(ph, o + dx) - ld32(ph, o)) * ih - ld32(m0, o);
+  T wa1 = ld32(z1, o) - (ld32(ph, o + (gi == g.n2 - 1 ? 0u : fp)) - ld32(ph, o)) * ih - ld32(m1, o);
+  const int rend = min(kRunY, sd.si - r0);
+  for (int rr = 0; rr < rend; ++rr, o += fp, ++gi) {
+    const bool lasty = gi == g.n2 - 1;                  // uniform over the wavefront
+    const unsigned dy = lasty ? 0u : fp;                // (grad phi)_y in row r; lower neighbour
+    const unsigned dys = (lasty || gi + 1 == g.n2 - 1) ? 0u : fp;  // (grad phi)_y in row r + 1
+    const unsigned oe = o + de, os = o + dy;
+    const T we0 = ld32(z0, oe) - (ld32(ph, oe + dxe) - ld32(ph, oe)) * ih - ld32(m0, oe);
+    const T we1 = ld32(z1, oe) - (ld32(ph, oe + dy) - ld32(ph, oe)) * ih - ld32(m1, oe);
+    const T wd0 = ld32(z0, os) - (ld32(ph, os + dx) - ld32(ph, os)) * ih - ld32(m0, os);
+    const T wd1 = ld32(z1, os) - (ld32(ph, os + dys) - ld32(ph, os)) * ih - ld32(m1, os);
+    const T px0 = lastx ? T(0) : (we0 - wa0) * ih;
+    const T px1 = lastx ? T(0) : (we1 - wa1) * ih;
+    const T py0 = lasty ? T(0) : (wd0 - wa0) * ih;
+    const T py1 = lasty ? T(0) : (wd1 - wa1) * ih;
+    const T th = thx * thy[r0 + rr];
+    const T s0 = dual_scale(th, t, px0 * px0 + py0 * py0);
+    const T s1 = dual_scale(th, t, px1 * px1 + py1 * py1);
+    st32(o0, o, s0 * (ld32(v0, o) + t * px0));
+    st32(o1, o, s0 * (ld32(v1, o) + t * py0));
+    st32(o2, o, s1 * (ld32(v2, o) + t * px1));
+    st32(o3, o, s1 * (ld32(v3, o) + t * py1));
+    wa0 = wd0;
+    wa1 = wd1;
   }
 }
 template <typename T>
 void launch_sub_update1(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* z,
                         const T* phi, const T* omega, T* v_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_update1<T>, grid2d(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, c, v, z, phi, omega, v_out);
+  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, c, v, z, phi, omega, v_out);
   TVS_LAUNCH_CHECK();
 }
 
@@ -467,39 +533,73 @@ void launch_sub2_prologue(const SubFrames& sf, Grid g, T inv_h, const T* p, cons
 }
 
 // Inner iteration of Algorithm 3 for the ROF dual: psi = grad(div v + b) on
-// the subdomain, v <- theta (v + t psi) / (theta + t |psi|)
+// the subdomain, v <- theta (v + t psi) / (theta + t |psi|).  Row runs as in
+// the Step-1 update: s = div v + b at (r + 1, q) and v there are carried to
+// the next row.  Terms of the backward differences that fall outside the
+// frame support, or on the grid's last row/column, are selected to 0; their
+// loads use clamped offsets inside the frame.
 template <typename T>
-__global__ void k_sub2_update(SubFrames sf, Grid g, StepScalars<T> cs, const T* __restrict__ v,
-                              const T* __restrict__ bfr, T* __restrict__ v_out) {
-  const int q = blockIdx.x * kBX + threadIdx.x, r = blockIdx.y * kBY + threadIdx.y;
+__global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, Grid g, StepScalars<T> cs,
+                                                         const T* __restrict__ v,
+                                                         const T* __restrict__ bfr,
+                                                         T* __restrict__ v_out) {
+  const int q = blockIdx.x * kBX + threadIdx.x;
+  const int r0 = __builtin_amdgcn_readfirstlane((blockIdx.y * kBY + threadIdx.y) * kRunY);
   const SubDesc sd = sf.subs[blockIdx.z];
-  if (r >= sd.si || q >= sd.sj) return;
-  const long long lo = (long long)r * sf.fp + q;
-  const T* vx = v + (long long)blockIdx.z * 2 * sf.plane;
-  const T* vy = vx + sf.plane;
-  const T* bb = bfr + (long long)blockIdx.z * sf.plane;
-  const int gi = sd.i0 + r, gj = sd.j0 + q;
-  // s(o) = div v + b at frame offset o of grid point (ii, jj)
-  auto s_at = [&](long long o, int rr, int qq, int ii, int jj) {
-    const T a = (jj == g.n1 - 1) ? T(0) : vx[o];
-    const T am = (qq > 0) ? vx[o - 1] : T(0);
-    const T c = (ii == g.n2 - 1) ? T(0) : vy[o];
-    const T cm = (rr > 0) ? vy[o - sf.fp] : T(0);
-    return ((a - am) + (c - cm)) * cs.inv_h + bb[o];
-  };
-  const T s0 = s_at(lo, r, q, gi, gj);
-  const T px = (gj == g.n1 - 1) ? T(0) : (s_at(lo + 1, r, q + 1, gi, gj + 1) - s0) * cs.inv_h;
-  const T py = (gi == g.n2 - 1) ? T(0) : (s_at(lo + sf.fp, r + 1, q, gi + 1, gj) - s0) * cs.inv_h;
-  const T th = theta_at<T>(sf, sd, gi, gj);
-  const T den = th + cs.t * sqrt(px * px + py * py);
-  T* ox = v_out + (long long)blockIdx.z * 2 * sf.plane;
-  ox[lo] = th * (vx[lo] + cs.t * px) / den;
-  ox[sf.plane + lo] = th * (vy[lo] + cs.t * py) / den;
+  if (r0 >= sd.si || q >= sd.sj) return;
+  const unsigned fp = sf.fp, pl = unsigned(sf.plane);
+  const size_t box = blockIdx.z;
+  const T* vx = v + box * 2 * pl;
+  const T* vy = vx + pl;
+  const T* bb = bfr + box * pl;
+  T* ox = v_out + box * 2 * pl;
+  T* oy = ox + pl;
+  const T* thy = theta_rows<T>(sf) + sd.m2 * sf.fr;
+  const T ih = cs.inv_h, t = cs.t;
+  const int gj = sd.j0 + q;
+  const bool lastx = gj == g.n1 - 1;
+  const bool lastx1 = lastx || gj + 1 == g.n1 - 1;  // right neighbour on the last column
+  const unsigned de = lastx ? 0u : 1u;
+  const unsigned dl = q > 0 ? 1u : 0u;             // left neighbour inside the frame
+  const T thx = theta_cols<T>(sf)[sd.m1 * sf.fp + q];
+  unsigned o = unsigned(r0) * fp + unsigned(q);
+  int gi = sd.i0 + r0;
+  // s, vx and vy at (r0, q); vy at (r0 - 1, q)
+  T xa = ld32(vx, o), ya = ld32(vy, o);
+  T yu = r0 > 0 ? ld32(vy, o - fp) : T(0);
+  const T xl0 = q > 0 ? ld32(vx, o - dl) : T(0);
+  T sa = (((lastx ? T(0) : xa) - xl0) + ((gi == g.n2 - 1 ? T(0) : ya) - yu)) * ih + ld32(bb, o);
+  const int rend = min(kRunY, sd.si - r0);
+  for (int rr = 0; rr < rend; ++rr, o += fp, ++gi) {
+    const int r = r0 + rr;
+    const bool lasty = gi == g.n2 - 1;
+    const unsigned dy = lasty ? 0u : fp;
+    const unsigned du = r > 0 ? fp : 0u;
+    const unsigned oe = o + de, os = o + dy;
+    // right neighbour (r, q + 1): vx(r, q+1) - vx(r, q) + vy(r, q+1) - vy(r-1, q+1)
+    const T xe = ld32(vx, oe), ye = ld32(vy, oe), yeu = ld32(vy, oe - du);
+    const T se = (((lastx1 ? T(0) : xe) - xa) + ((lasty ? T(0) : ye) - (r > 0 ? yeu : T(0)))) * ih +
+                 ld32(bb, oe);
+    // lower neighbour (r + 1, q): vx(r+1, q) - vx(r+1, q-1) + vy(r+1, q) - vy(r, q)
+    const T xs = ld32(vx, os), xsl = ld32(vx, os - dl), ys = ld32(vy, os);
+    const bool lasty1 = lasty || gi + 1 == g.n2 - 1;
+    const T ss = (((lastx ? T(0) : xs) - (q > 0 ? xsl : T(0))) + ((lasty1 ? T(0) : ys) - ya)) * ih +
+                 ld32(bb, os);
+    const T px = lastx ? T(0) : (se - sa) * ih;
+    const T py = lasty ? T(0) : (ss - sa) * ih;
+    const T th = thx * thy[r];
+    const T sc = dual_scale(th, t, px * px + py * py);
+    st32(ox, o, sc * (xa + t * px));
+    st32(oy, o, sc * (ya + t * py));
+    sa = ss;
+    xa = xs;
+    ya = ys;
+  }
 }
 template <typename T>
 void launch_sub2_update(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* b,
                         T* v_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub2_update<T>, grid2d(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, c, v, b, v_out);
+  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, c, v, b, v_out);
   TVS_LAUNCH_CHECK();
 }
 

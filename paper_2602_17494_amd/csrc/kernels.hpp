@@ -55,13 +55,25 @@ void launch_scale(const T* in, long long n, T a, T* out, hipStream_t s);
 
 // Step 1 per-subdomain kernels (4-plane v frames, 2-plane z and omega frames,
 // 1-plane phi frames; frame pitch fp, frame rows fr).
+// Partition-of-unity factors are tabulated per frame row and column:
+// theta_m(i0 + r, j0 + q) = thy[m2 * fr + r] * thx[m1 * fp + q].
 struct SubFrames {
   const SubDesc* subs;
   int nsub;
   int fr, fp;                 // frame rows and pitch
   long long plane;            // fr * fp
   AxisLayout ay, ax;          // the partition of unity
+  const float* thy_f;         // theta tables in both compute types
+  const float* thx_f;
+  const double* thy_d;
+  const double* thx_d;
 };
+template <typename T> __device__ __forceinline__ const T* theta_rows(const SubFrames& sf);
+template <> __device__ __forceinline__ const float* theta_rows<float>(const SubFrames& sf) { return sf.thy_f; }
+template <> __device__ __forceinline__ const double* theta_rows<double>(const SubFrames& sf) { return sf.thy_d; }
+template <typename T> __device__ __forceinline__ const T* theta_cols(const SubFrames& sf);
+template <> __device__ __forceinline__ const float* theta_cols<float>(const SubFrames& sf) { return sf.thx_f; }
+template <> __device__ __forceinline__ const double* theta_cols<double>(const SubFrames& sf) { return sf.thx_d; }
 template <typename T>
 void launch_sub_theta_p(const SubFrames& sf, Grid g, const T* p, int planes, T* v, hipStream_t s);
 template <typename T>
