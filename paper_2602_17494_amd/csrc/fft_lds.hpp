@@ -1,11 +1,12 @@
-// Mixed-radix (2, 3, 4, 5, 8, 9) Stockham FFT held entirely in LDS.
+// Mixed-radix (2, 3, 4, 5, 8, 9) Stockham FFT staged in LDS.
 //
 // A workgroup of NT threads transforms `batch` independent complex sequences
-// of length n stored in LDS at buf + b * stride.  Two LDS buffers are used in
-// turn: each pass reads every butterfly's inputs from one buffer and writes
-// the outputs to their self-sorting positions (Stockham autosort) in the
-// other, with one barrier per pass; the final data may end in either buffer
-// and fft_lds returns it.  Twiddles come from a table tw[m] = exp(-2 pi i m/n)
+// of length n.  Two LDS buffers are used in turn: each pass reads every
+// butterfly's inputs from one buffer and writes the outputs to their
+// self-sorting positions (Stockham autosort) in the other, with one barrier
+// per pass.  The first pass may read its inputs from anywhere (global memory,
+// a fused pre-processing step) and the last pass may write anywhere, which
+// saves the LDS round trips of loading and storing the data.  Twiddles come from a table tw[m] = exp(-2 pi i m/n)
 // in global memory (L1/L2 resident).  Forward transforms use the exp(-...)
 // convention and are unnormalised; the inverse uses exp(+...).
 #pragma once
@@ -129,10 +130,15 @@ __device__ __forceinline__ void butterfly(cplx<T>* v, bool inv) {
   }
 }
 
-template <typename T, int NT, int R>
-__device__ __forceinline__ void fft_pass(const cplx<T>* src, cplx<T>* dst, int stride, int batch,
-                                         FastDiv fls, FastDiv fnbf, int twstep,
-                                         const cplx<T>* __restrict__ tw, bool inv) {
+// One Stockham pass of radix R over `batch` sequences of length n = R * nbf:
+// butterfly j of sequence b takes inputs j + t * nbf (t < R), twiddled by
+// w^(k t twstep) with k = j mod Ls, and writes outputs g Ls R + k + t Ls,
+// g = j / Ls.  Inputs come from ld(b, index, t) and outputs go to
+// st(b, index, value), so a pass can read or write global memory directly
+// (t lets a loader pick per-input data it prepared in registers).
+template <typename T, int NT, int R, typename LD, typename ST>
+__device__ __forceinline__ void fft_pass_io(LD& ld, ST& st, int batch, FastDiv fls, FastDiv fnbf,
+                                            int twstep, const cplx<T>* __restrict__ tw, bool inv) {
   using C = cplx<T>;
   const int nbf = fnbf.d, Ls = fls.d;
   const int total = nbf * batch;
@@ -141,24 +147,97 @@ __device__ __forceinline__ void fft_pass(const cplx<T>* src, cplx<T>* dst, int s
     const int j = jj - b * nbf;
     const int g = fls.div(j);
     const int k = j - g * Ls;
-    const C* x = src + b * stride;
     C v[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      C c = x[j + t * nbf];
-      if (t > 0) {
+    for (int t = 0; t < R; ++t) v[t] = ld(b, j + t * nbf, t);
+    if (Ls > 1) {  // the first pass (Ls == 1) has k == 0: no twiddles
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
         C w = tw[k * t * twstep];
         if (inv) w.y = -w.y;
-        c = cmul(c, w);
+        v[t] = cmul(v[t], w);
       }
-      v[t] = c;
     }
     butterfly<R, T>(v, inv);
-    C* y = dst + b * stride;
     const int base = g * Ls * R + k;
 #pragma unroll
-    for (int t = 0; t < R; ++t) y[base + t * Ls] = v[t];
+    for (int t = 0; t < R; ++t) st(b, base + t * Ls, v[t]);
   }
+}
+
+template <typename T, int NT, typename LD, typename ST>
+__device__ __forceinline__ void fft_pass_radix(int radix, LD& ld, ST& st, int batch, FastDiv fls,
+                                               FastDiv fnbf, int twstep,
+                                               const cplx<T>* __restrict__ tw, bool inv) {
+  switch (radix) {
+    case 8: fft_pass_io<T, NT, 8>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    case 9: fft_pass_io<T, NT, 9>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    case 4: fft_pass_io<T, NT, 4>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    case 2: fft_pass_io<T, NT, 2>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    case 3: fft_pass_io<T, NT, 3>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    default: fft_pass_io<T, NT, 5>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+  }
+}
+
+// Sequence s, element i of an LDS buffer holding sequences `stride` apart.
+template <typename T>
+struct LdsSeq {
+  cplx<T>* p;
+  int stride;
+  __device__ __forceinline__ cplx<T> operator()(int s, int i, int) const { return p[s * stride + i]; }
+  __device__ __forceinline__ void operator()(int s, int i, cplx<T> v) const { p[s * stride + i] = v; }
+};
+
+// Passes 1 .. npass-1 of descriptor d (npass >= 2), after pass 0 has written
+// LDS buffer p0 and a barrier: pass p < npass-1 writes p0 (p even) or p1 (p
+// odd), with a barrier after it; the last pass writes through `last`.
+template <typename T, int NT, typename ST>
+__device__ __forceinline__ void fft_run_tail(const FftDesc& d, ST& last, cplx<T>* p0, cplx<T>* p1,
+                                             int stride, int batch, const cplx<T>* __restrict__ tw,
+                                             bool inv) {
+  const int np = d.npass;
+  for (int p = 1; p < np - 1; ++p) {
+    LdsSeq<T> i{(p & 1) ? p0 : p1, stride}, o{(p & 1) ? p1 : p0, stride};
+    fft_pass_radix<T, NT>(d.radix[p], i, o, batch, d.ls[p], d.nbf[p], d.twstep[p], tw, inv);
+    __syncthreads();
+  }
+  LdsSeq<T> i{((np - 1) & 1) ? p0 : p1, stride};
+  fft_pass_radix<T, NT>(d.radix[np - 1], i, last, batch, d.ls[np - 1], d.nbf[np - 1],
+                        d.twstep[np - 1], tw, inv);
+}
+
+// All passes of descriptor d.  Pass 0 reads through `first`; pass p < npass-1
+// writes LDS buffer p0 (p even) or p1 (p odd), with a barrier after it; the
+// last pass writes through `last`.  `first` must not read a buffer that pass
+// 0 writes, and whatever it reads from LDS must be complete (barrier) before
+// the call.
+template <typename T, int NT, typename LD, typename ST>
+__device__ __forceinline__ void fft_run(const FftDesc& d, LD& first, ST& last, cplx<T>* p0,
+                                        cplx<T>* p1, int stride, int batch,
+                                        const cplx<T>* __restrict__ tw, bool inv) {
+  if (d.npass == 1) {
+    fft_pass_radix<T, NT>(d.radix[0], first, last, batch, d.ls[0], d.nbf[0], d.twstep[0], tw, inv);
+    return;
+  }
+  {
+    LdsSeq<T> o{p0, stride};
+    fft_pass_radix<T, NT>(d.radix[0], first, o, batch, d.ls[0], d.nbf[0], d.twstep[0], tw, inv);
+  }
+  __syncthreads();
+  fft_run_tail<T, NT>(d, last, p0, p1, stride, batch, tw, inv);
+}
+
+// As fft_run with the result left in LDS; returns the buffer that holds it
+// (p0 or p1) and ends with a barrier.
+template <typename T, int NT, typename LD>
+__device__ __forceinline__ cplx<T>* fft_run_to_lds(const FftDesc& d, LD& first, cplx<T>* p0,
+                                                   cplx<T>* p1, int stride, int batch,
+                                                   const cplx<T>* __restrict__ tw, bool inv) {
+  cplx<T>* res = ((d.npass - 1) & 1) ? p1 : p0;
+  LdsSeq<T> o{res, stride};
+  fft_run<T, NT>(d, first, o, p0, p1, stride, batch, tw, inv);
+  __syncthreads();
+  return res;
 }
 
 // Transform `batch` sequences of length d.n held in buffer a (sequence b at
@@ -166,27 +245,10 @@ __device__ __forceinline__ void fft_pass(const cplx<T>* src, cplx<T>* dst, int s
 // holds the result.  The caller's writes to a must be complete (barrier)
 // before the call; the call ends with a barrier.
 template <typename T, int NT>
-__device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* bbuf, const FftDesc& d, int stride, int batch,
-                            const cplx<T>* __restrict__ tw, bool inv) {
-  cplx<T>* src = a;
-  cplx<T>* dst = bbuf;
-  for (int p = 0; p < d.npass; ++p) {
-    const FastDiv ls = d.ls[p], nb = d.nbf[p];
-    const int ts = d.twstep[p];
-    switch (d.radix[p]) {
-      case 8: fft_pass<T, NT, 8>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
-      case 9: fft_pass<T, NT, 9>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
-      case 4: fft_pass<T, NT, 4>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
-      case 2: fft_pass<T, NT, 2>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
-      case 3: fft_pass<T, NT, 3>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
-      default: fft_pass<T, NT, 5>(src, dst, stride, batch, ls, nb, ts, tw, inv); break;
-    }
-    __syncthreads();
-    cplx<T>* t = src;
-    src = dst;
-    dst = t;
-  }
-  return src;
+__device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* bbuf, const FftDesc& d, int stride,
+                                            int batch, const cplx<T>* __restrict__ tw, bool inv) {
+  LdsSeq<T> in{a, stride};
+  return fft_run_to_lds<T, NT>(d, in, bbuf, a, stride, batch, tw, inv);
 }
 
 }  // namespace tvs

@@ -298,6 +298,10 @@ __device__ __forceinline__ const cplx<T>* stage_twiddles(cplx<T>* lds, const cpl
   }
 }
 
+// Row transforms of the source: rows 2m and 2m+1 of div u (zero outside the
+// box) form the real and imaginary parts of one complex sequence; the half
+// spectra of the two rows are separated from the packed result and stored
+// column-major.
 template <typename T, int NT, bool TWL>
 __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
                                                        Frame uf) {
@@ -310,6 +314,8 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * ppw * Lj, d.tw_j, Lj);
+  // all NT threads stage the packed rows (the first pass has fewer butterflies
+  // than threads, and these loads are the latency-bound part)
   for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
     const int qq = d.fd_Lj.div(e), c = e - qq * Lj;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
@@ -334,6 +340,55 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   }
 }
 
+// Phi(ki) from X(ki), X(-ki) and the four window spectra at ki.
+template <typename T>
+__device__ __forceinline__ cplx<T> combine_phi(cplx<T> x, cplx<T> xn, cplx<T> k00, cplx<T> k01,
+                                               cplx<T> k10, cplx<T> k11) {
+  cplx<T> acc = cmul(x, k00);
+  acc = cadd(acc, cmul(cconj(xn), k01));
+  acc = cadd(acc, cmul(xn, k10));
+  return cadd(acc, cmul(cconj(x), k11));
+}
+
+// Column pass with the window spectra of the first inverse pass (radix R,
+// one butterfly per thread: column c, index j) loaded up front.
+template <typename T, int NT, int R, typename LD, typename ST>
+__device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, ST& st_s,
+                                                cplx<T>* bufa, cplx<T>* bufb,
+                                                const cplx<T>* const (&sp)[4], int c, int j,
+                                                bool act, const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  const int Li = d.Li, cpw = d.cpw, nbf = d.fi.nbf[0].d;
+  C k[4][R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int o = c * Li + j + t * nbf;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) k[m][t] = act ? sp[m][o] : C{T(0), T(0)};
+  }
+  const C* X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
+  C* Y = (X == bufa) ? bufb : bufa;
+  if (act) {
+    C v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int ki = j + t * nbf;
+      v[t] = combine_phi(X[c * Li + ki], X[c * Li + (ki == 0 ? 0 : Li - ki)], k[0][t], k[1][t],
+                         k[2][t], k[3][t]);
+    }
+    butterfly<R, T>(v, true);
+#pragma unroll
+    for (int t = 0; t < R; ++t) Y[c * Li + j * R + t] = v[t];  // Ls = 1: output j R + t
+  }
+  __syncthreads();
+  fft_run_tail<T, NT>(d.fi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
+}
+
+// Column transforms, spectral combination and inverse column transforms for
+// `cpw` columns of one box.  The forward transform loads the box's ni rows
+// of each column (zero beyond), the first inverse pass forms
+//   Phi = X K00 + conj(X(-ki)) K01 + X(-ki) K10 + conj(X) K11
+// as it loads, and the last inverse pass stores the box's ni rows back.
 // Launch order: the box index is the fastest grid dimension, so consecutive
 // workgroups (dealt round-robin to the eight XCDs) work on the same column
 // tile of neighbouring boxes; boxes of one subdomain column then share an
@@ -345,49 +400,51 @@ __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   C* bufa = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
-  const int Li = d.Li, Lh = d.Lh, cpw = d.cpw;
+  const int Li = d.Li, Lh = d.Lh, cpw = d.cpw, rows_max = d.rows_max;
   C* bufb = bufa + cpw * Li;
   const int k0 = blockIdx.y * cpw;
+  const int ncol = min(cpw, Lh - k0);
   const C* tw = stage_twiddles<T, NT, TWL>(bufa + 2 * cpw * Li, d.tw_i, Li);
-  C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
-  for (int c = 0; c < cpw; ++c) {
-    const int k = k0 + c;
-    const C* col = S + static_cast<size_t>(k) * d.rows_max;
-    for (int r = threadIdx.x; r < Li; r += NT)
-      bufa[c * Li + r] = (r < bx.ni && k < Lh) ? col[r] : C{T(0), T(0)};
-  }
-  __syncthreads();
-  const C* X = fft_lds<T, NT>(bufa, bufb, d.fi, Li, cpw, tw, false);
-  C* Y = (X == bufa) ? bufb : bufa;
-  // Phi = X K00 + conj(X(-ki)) K01 + X(-ki) K10 + conj(X) K11
-  const size_t slot_sz = static_cast<size_t>(Li) * Lh;
-  const C* s00 = d.spec + static_cast<size_t>(bx.k00) * slot_sz;
-  const C* s01 = d.spec + static_cast<size_t>(bx.k01) * slot_sz;
-  const C* s10 = d.spec + static_cast<size_t>(bx.k10) * slot_sz;
-  const C* s11 = d.spec + static_cast<size_t>(bx.k11) * slot_sz;
-  for (int c = 0; c < cpw; ++c) {
-    const int k = k0 + c;
-    if (k >= Lh) break;
-    const size_t o0 = static_cast<size_t>(k) * Li;
-    for (int ki = threadIdx.x; ki < Li; ki += NT) {
-      const C x = X[c * Li + ki];
-      const C xn = X[c * Li + (ki == 0 ? 0 : Li - ki)];
-      const size_t o = o0 + ki;
-      C acc = cmul(x, s00[o]);
-      acc = cadd(acc, cmul(cconj(xn), s01[o]));
-      acc = cadd(acc, cmul(xn, s10[o]));
-      acc = cadd(acc, cmul(cconj(x), s11[o]));
-      Y[c * Li + ki] = acc;
+  C* S = d.S + static_cast<size_t>(b) * rows_max * Lh + static_cast<size_t>(k0) * rows_max;
+  const size_t slot_sz = static_cast<size_t>(Li) * Lh, col0 = static_cast<size_t>(k0) * Li;
+  const C* s00 = d.spec + static_cast<size_t>(bx.k00) * slot_sz + col0;
+  const C* s01 = d.spec + static_cast<size_t>(bx.k01) * slot_sz + col0;
+  const C* s10 = d.spec + static_cast<size_t>(bx.k10) * slot_sz + col0;
+  const C* s11 = d.spec + static_cast<size_t>(bx.k11) * slot_sz + col0;
+  auto ld_s = [&](int c, int r, int) -> C {
+    return (c < ncol && r < bx.ni) ? S[c * rows_max + r] : C{T(0), T(0)};
+  };
+  auto st_s = [&](int c, int r, C v) {
+    if (c < ncol && r < bx.ni) S[c * rows_max + r] = v;
+  };
+  if constexpr (sizeof(T) == 4) {
+  const int r0 = d.fi.radix[0], nbf0 = d.fi.nbf[0].d;
+  if (d.fi.npass >= 2 && nbf0 * cpw <= NT) {
+    // One butterfly per thread in the first inverse pass: its window-spectrum
+    // values are loaded before the forward transform, so that their latency
+    // overlaps it.
+    const int c = d.fi.nbf[0].div(threadIdx.x), j = threadIdx.x - c * nbf0;
+    const bool act = threadIdx.x < nbf0 * cpw && c < ncol;
+    const cplx<T>* sp[4] = {s00, s01, s10, s11};
+    switch (r0) {
+      case 8: cols_prefetched<T, NT, 8>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+      case 9: cols_prefetched<T, NT, 9>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+      case 4: cols_prefetched<T, NT, 4>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+      case 2: cols_prefetched<T, NT, 2>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+      case 3: cols_prefetched<T, NT, 3>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+      default: cols_prefetched<T, NT, 5>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
     }
+    return;
   }
-  __syncthreads();
-  const C* Z = fft_lds<T, NT>(Y, const_cast<C*>(X), d.fi, Li, cpw, tw, true);
-  for (int c = 0; c < cpw; ++c) {
-    const int k = k0 + c;
-    if (k >= Lh) break;
-    C* col = S + static_cast<size_t>(k) * d.rows_max;
-    for (int r = threadIdx.x; r < bx.ni; r += NT) col[r] = Z[c * Li + r];
   }
+  const C* X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
+  C* Y = (X == bufa) ? bufb : bufa;
+  auto ld_phi = [&](int c, int ki, int) -> C {
+    if (c >= ncol) return C{T(0), T(0)};
+    const int o = c * Li + ki;
+    return combine_phi(X[o], X[c * Li + (ki == 0 ? 0 : Li - ki)], s00[o], s01[o], s10[o], s11[o]);
+  };
+  fft_run<T, NT>(d.fi, ld_phi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
 }
 
 template <typename T, int NT, bool TWL>
@@ -403,27 +460,23 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * ppw * Lj, d.tw_j, Lj);
   const C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   const int half = Lj / 2;
-  for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
-    const int k = d.fd_ppw.div(e), qq = e - k * ppw;
+  auto ld = [&](int qq, int k, int) -> C {
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const int kk = k <= half ? k : Lj - k;
     const C* col = S + static_cast<size_t>(kk) * d.rows_max;
     const C a = ra < bx.ni ? col[ra] : C{T(0), T(0)};
     const C c = rb < bx.ni ? col[rb] : C{T(0), T(0)};
-    buf[qq * Lj + k] = k <= half ? C{a.x - c.y, a.y + c.x} : C{a.x + c.y, c.x - a.y};
-  }
-  __syncthreads();
-  const C* res = fft_lds<T, NT>(buf, buf + ppw * Lj, d.fj, Lj, ppw, tw, true);
+    return k <= half ? C{a.x - c.y, a.y + c.x} : C{a.x + c.y, c.x - a.y};
+  };
   T* out = phi + b * pf.box_stride;
-  for (int qq = 0; qq < ppw; ++qq) {
+  auto st = [&](int qq, int c, C z) {
     const int ra = 2 * (q0 + qq), rb = ra + 1;
-    if (ra >= bx.ni) break;
-    for (int c = threadIdx.x; c < bx.nj; c += NT) {
-      const C z = res[qq * Lj + c];
+    if (ra < bx.ni && c < bx.nj) {
       out[static_cast<long long>(ra) * pf.pitch + c] = z.x;
       if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
     }
-  }
+  };
+  fft_run<T, NT>(d.fj, ld, st, buf, buf + ppw * Lj, Lj, ppw, tw, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -60,7 +60,11 @@ def test_2048_reduced_counts_against_oracle(ctx, dtype, tol_d, tol_tau):
     assert np.abs(d.sum(axis=1) - g["d_rowsum"]).max() < tol_d * N
     assert np.abs(tau[1].sum(axis=1) - g["tau2_rowsum"]).max() < tol_tau * N
     assert st[0]["energy"] == pytest.approx(float(g["energy1"][-1]), rel=1e-9 if dtype == "f64" else 1e-5)
-    assert st[1]["energy"] == pytest.approx(float(g["energy2"][-1]), rel=1e-9 if dtype == "f64" else 1e-5)
+    # The Step-2 dual energy ||div p - f||^2 is dominated by f = alpha (d0 - g),
+    # and in float32 g is a row prefix sum of N = 2048 terms: its rounding is
+    # about sqrt(N) u ~ 3e-6 relative per pixel (u = 2^-24), which enters the
+    # energy twice and through the float32 p; 5e-5 bounds that with margin.
+    assert st[1]["energy"] == pytest.approx(float(g["energy2"][-1]), rel=1e-9 if dtype == "f64" else 5e-5)
 
 
 def test_2048_full_counts_properties(ctx):
