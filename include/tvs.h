@@ -160,13 +160,16 @@ int tvs_schwarz_solve(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dt
 int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dtype dtype,
                          double h, void* u_out, void* stream);
 
-/* Diagnostics: kernel timing.  While enabled, every launch of an
- * instrumented kernel class is bracketed by two HIP events recorded on the
- * call's stream, and credited with the launch's algorithmic bytes (the data
- * the kernel must read and write at minimum; the formulas are listed with
- * each kernel in the library sources).  Enabling it adds two event records
- * per instrumented launch and no synchronisation.
- *   tvs_timing_enable  switch recording on (1) or off (0)
+/* Diagnostics: kernel timing.  While enabled, one launch in every `enable`
+ * launches of each instrumented kernel class (the 1st, the (enable+1)-th,
+ * ...) is bracketed by two HIP events recorded on the call's stream, and
+ * credited with the launch's algorithmic bytes (the data the kernel must read
+ * and write at minimum; the formulas are listed with each kernel in the
+ * library sources).  Enabling it adds two event records per timed launch;
+ * every 64 pending records of a class, the older half is folded in, which
+ * waits for launches that are by then long finished.
+ *   tvs_timing_enable  enable = 0: off; enable = k >= 1: time every k-th
+ *                      launch of each class (1: every launch); < 0: error
  *   tvs_timing_reset   drop everything recorded so far
  *   tvs_timing_count   wait for the recorded events and return the number of
  *                      kernel classes (>= 0), or a negative error code

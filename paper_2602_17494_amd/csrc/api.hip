@@ -719,7 +719,9 @@ int tvs_schwarz_solve(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dt
 int tvs_timing_enable(tvs_ctx* ctx, int enable) {
   return guarded([&] {
     if (!ctx) throw Error(TVS_EINVAL, "NULL context");
+    if (enable < 0) throw Error(TVS_EINVAL, "timing: enable must be >= 0");
     ctx->timer.on = enable != 0;
+    ctx->timer.every = enable > 0 ? enable : 1;
   });
 }
 

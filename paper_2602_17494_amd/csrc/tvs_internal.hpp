@@ -103,10 +103,12 @@ struct KernelTimer {
   };
   struct Acc {
     std::vector<Rec> pending;
-    long long launches = 0;
+    long long calls = 0;     // instrumented calls seen, timed or not
+    long long launches = 0;  // timed launches folded in
     double ms = 0, bytes = 0;
   };
   bool on = false;
+  int every = 1;  // time one launch in `every` of each class
   std::vector<std::pair<std::string, Acc>> accs;
   std::vector<hipEvent_t> pool;
 
@@ -133,27 +135,38 @@ struct KernelTimer {
       launch();
       return;
     }
+    Acc& a = t->acc(name);
+    if (a.calls++ % t->every != 0) {
+      launch();
+      return;
+    }
+    // keep the number of outstanding events bounded: the oldest records
+    // are long finished when this many have queued up behind them
+    if (a.pending.size() >= 64) t->fold_front(a, a.pending.size() / 2);
     Rec r{t->get_event(), t->get_event(), bytes};
     if (hipEventRecord(r.a, s) != hipSuccess) throw Error(-3, "hipEventRecord failed");
     launch();
     if (hipEventRecord(r.b, s) != hipSuccess) throw Error(-3, "hipEventRecord failed");
-    t->acc(name).pending.push_back(r);
+    a.pending.push_back(r);
+  }
+  // Fold the first n pending records of a into its totals (waits for them).
+  void fold_front(Acc& a, size_t n) {
+    for (size_t i = 0; i < n; ++i) {
+      Rec& r = a.pending[i];
+      if (hipEventSynchronize(r.b) != hipSuccess) throw Error(-3, "hipEventSynchronize failed");
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) throw Error(-3, "hipEventElapsedTime failed");
+      a.ms += ms;
+      a.bytes += r.bytes;
+      a.launches += 1;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    a.pending.erase(a.pending.begin(), a.pending.begin() + static_cast<long>(n));
   }
   // Fold finished records into the totals (waits for their events).
   void collect() {
-    for (auto& kv : accs) {
-      for (auto& r : kv.second.pending) {
-        if (hipEventSynchronize(r.b) != hipSuccess) throw Error(-3, "hipEventSynchronize failed");
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) throw Error(-3, "hipEventElapsedTime failed");
-        kv.second.ms += ms;
-        kv.second.bytes += r.bytes;
-        kv.second.launches += 1;
-        pool.push_back(r.a);
-        pool.push_back(r.b);
-      }
-      kv.second.pending.clear();
-    }
+    for (auto& kv : accs) fold_front(kv.second, kv.second.pending.size());
   }
   void reset() {
     collect();

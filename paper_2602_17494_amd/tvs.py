@@ -200,9 +200,12 @@ class Context:
                                         tau_p, st if stats else None, _stream(d0.device)))
         return d_out, ([st[0].as_dict(), st[1].as_dict()] if stats else None)
 
-    def timing(self, enable=True):
-        """Switch kernel timing on or off (HIP events around instrumented launches)."""
-        _check(load().tvs_timing_enable(self._h, 1 if enable else 0))
+    def timing(self, enable=True, every=1):
+        """Switch kernel timing on or off (HIP events around one in `every`
+        launches of each instrumented kernel class)."""
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        _check(load().tvs_timing_enable(self._h, int(every) if enable else 0))
 
     def timing_reset(self):
         _check(load().tvs_timing_reset(self._h))
