@@ -179,13 +179,21 @@ __device__ __forceinline__ void fft_pass_radix(int radix, LD& ld, ST& st, int ba
   }
 }
 
+// Element e of an LDS transform buffer is stored at lds_swz(e): a bijection
+// within each aligned block of 32 elements (bits 0-4 are XORed with bits 3-7)
+// that spreads the strided accesses of the Stockham passes over the LDS
+// banks.  Buffers hold lds_round(n) elements so that blocks do not straddle
+// them.
+__device__ __forceinline__ int lds_swz(int e) { return e ^ ((e >> 3) & 7) ^ (((e >> 6) & 3) << 3); }
+__host__ __device__ constexpr int lds_round(int n) { return (n + 31) & ~31; }
+
 // Sequence s, element i of an LDS buffer holding sequences `stride` apart.
 template <typename T>
 struct LdsSeq {
   cplx<T>* p;
   int stride;
-  __device__ __forceinline__ cplx<T> operator()(int s, int i, int) const { return p[s * stride + i]; }
-  __device__ __forceinline__ void operator()(int s, int i, cplx<T> v) const { p[s * stride + i] = v; }
+  __device__ __forceinline__ cplx<T> operator()(int s, int i, int) const { return p[lds_swz(s * stride + i)]; }
+  __device__ __forceinline__ void operator()(int s, int i, cplx<T> v) const { p[lds_swz(s * stride + i)] = v; }
 };
 
 // Passes 1 .. npass-1 of descriptor d (npass >= 2), after pass 0 has written
@@ -241,8 +249,8 @@ __device__ __forceinline__ cplx<T>* fft_run_to_lds(const FftDesc& d, LD& first, 
 }
 
 // Transform `batch` sequences of length d.n held in buffer a (sequence b at
-// a + b * stride), using bbuf as the second buffer; returns the buffer that
-// holds the result.  The caller's writes to a must be complete (barrier)
+// elements b * stride of it, swizzled), using bbuf as the second buffer;
+// returns the buffer that holds the result.  The caller's writes to a must be complete (barrier)
 // before the call; the call ends with a barrier.
 template <typename T, int NT>
 __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* bbuf, const FftDesc& d, int stride,

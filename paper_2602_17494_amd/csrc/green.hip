@@ -210,15 +210,15 @@ __global__ __launch_bounds__(NT) void k_spec_rows(const double* __restrict__ g, 
     double va = 0.0, vb = 0.0;
     if (ra < Li) va = g_lookup(g, n2, n1, key.x + (ra < hi_i ? ra : ra - Li), key.y + dj);
     if (rb < Li) vb = g_lookup(g, n2, n1, key.x + (rb < hi_i ? rb : rb - Li), key.y + dj);
-    buf[qq * Lj + c] = cplx<double>{va, vb};
+    buf[lds_swz(qq * Lj + c)] = cplx<double>{va, vb};
   }
   __syncthreads();
-  const cplx<double>* res = fft_lds<double, NT>(buf, buf + ppw * Lj, fj, Lj, ppw, twj, false);
+  const cplx<double>* res = fft_lds<double, NT>(buf, buf + lds_round(ppw * Lj), fj, Lj, ppw, twj, false);
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int qq = e / Lh, k = e - qq * Lh;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
-    const cplx<double> z = res[qq * Lj + k];
-    const cplx<double> zn = res[qq * Lj + (k == 0 ? 0 : Lj - k)];
+    const cplx<double> z = res[lds_swz(qq * Lj + k)];
+    const cplx<double> zn = res[lds_swz(qq * Lj + (k == 0 ? 0 : Lj - k))];
     const size_t base = static_cast<size_t>(slot) * Li * Lh;
     if (ra < Li) out[base + static_cast<size_t>(ra) * Lh + k] = cplx<double>{0.5 * (z.x + zn.x), 0.5 * (z.y - zn.y)};
     if (rb < Li) out[base + static_cast<size_t>(rb) * Lh + k] = cplx<double>{0.5 * (z.y + zn.y), 0.5 * (zn.x - z.x)};
@@ -244,16 +244,16 @@ __global__ __launch_bounds__(NT) void k_spec_cols(const cplx<double>* __restrict
   for (int e = threadIdx.x; e < cpw * Li; e += NT) {
     const int r = e / cpw, c = e - r * cpw;
     const int k = k0 + c;
-    buf[c * Li + r] = (k < Lh) ? in[base + static_cast<size_t>(r) * Lh + k] : cplx<double>{0.0, 0.0};
+    buf[lds_swz(c * Li + r)] = (k < Lh) ? in[base + static_cast<size_t>(r) * Lh + k] : cplx<double>{0.0, 0.0};
   }
   __syncthreads();
-  const cplx<double>* res = fft_lds<double, NT>(buf, buf + cpw * Li, fi, Li, cpw, twi, false);
+  const cplx<double>* res = fft_lds<double, NT>(buf, buf + lds_round(cpw * Li), fi, Li, cpw, twi, false);
   const double scale = 1.0 / (double(Li) * double(Lj));
   for (int e = threadIdx.x; e < cpw * Li; e += NT) {
     const int c = e / Li, r = e - c * Li;
     const int k = k0 + c;
     if (k >= Lh) continue;
-    cplx<double> v = res[c * Li + r];
+    cplx<double> v = res[lds_swz(c * Li + r)];
     v.x *= scale;
     v.y *= scale;
     if (key.z >= 0) v = cmul(v, twi[(static_cast<long long>(r) * key.z) % Li]);
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
-  const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * ppw * Lj, d.tw_j, Lj);
+  const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
   // all NT threads stage the packed rows (the first pass has fewer butterflies
   // than threads, and these loads are the latency-bound part)
   for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
@@ -324,16 +324,16 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
       if (ra < bx.ni) va = div_at(u, uf, b, bx.i0 + ra, bx.j0 + c, ra, c, d.n2, d.n1, d.inv_h);
       if (rb < bx.ni) vb = div_at(u, uf, b, bx.i0 + rb, bx.j0 + c, rb, c, d.n2, d.n1, d.inv_h);
     }
-    buf[qq * Lj + c] = C{va, vb};
+    buf[lds_swz(qq * Lj + c)] = C{va, vb};
   }
   __syncthreads();
-  const C* res = fft_lds<T, NT>(buf, buf + ppw * Lj, d.fj, Lj, ppw, tw, false);
+  const C* res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
   C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int k = d.fd_ppw.div(e), qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
-    const C z = res[qq * Lj + k];
-    const C zn = res[qq * Lj + (k == 0 ? 0 : Lj - k)];
+    const C z = res[lds_swz(qq * Lj + k)];
+    const C zn = res[lds_swz(qq * Lj + (k == 0 ? 0 : Lj - k))];
     C* col = S + static_cast<size_t>(k) * d.rows_max;
     if (ra < bx.ni) col[ra] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
     if (rb < bx.ni) col[rb] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
@@ -373,12 +373,12 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       const int ki = j + t * nbf;
-      v[t] = combine_phi(X[c * Li + ki], X[c * Li + (ki == 0 ? 0 : Li - ki)], k[0][t], k[1][t],
+      v[t] = combine_phi(X[lds_swz(c * Li + ki)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))], k[0][t], k[1][t],
                          k[2][t], k[3][t]);
     }
     butterfly<R, T>(v, true);
 #pragma unroll
-    for (int t = 0; t < R; ++t) Y[c * Li + j * R + t] = v[t];  // Ls = 1: output j R + t
+    for (int t = 0; t < R; ++t) Y[lds_swz(c * Li + j * R + t)] = v[t];  // Ls = 1: output j R + t
   }
   __syncthreads();
   fft_run_tail<T, NT>(d.fi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
@@ -401,10 +401,10 @@ __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
   const int Li = d.Li, Lh = d.Lh, cpw = d.cpw, rows_max = d.rows_max;
-  C* bufb = bufa + cpw * Li;
+  C* bufb = bufa + lds_round(cpw * Li);
   const int k0 = blockIdx.y * cpw;
   const int ncol = min(cpw, Lh - k0);
-  const C* tw = stage_twiddles<T, NT, TWL>(bufa + 2 * cpw * Li, d.tw_i, Li);
+  const C* tw = stage_twiddles<T, NT, TWL>(bufa + 2 * lds_round(cpw * Li), d.tw_i, Li);
   C* S = d.S + static_cast<size_t>(b) * rows_max * Lh + static_cast<size_t>(k0) * rows_max;
   const size_t slot_sz = static_cast<size_t>(Li) * Lh, col0 = static_cast<size_t>(k0) * Li;
   const C* s00 = d.spec + static_cast<size_t>(bx.k00) * slot_sz + col0;
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   auto ld_phi = [&](int c, int ki, int) -> C {
     if (c >= ncol) return C{T(0), T(0)};
     const int o = c * Li + ki;
-    return combine_phi(X[o], X[c * Li + (ki == 0 ? 0 : Li - ki)], s00[o], s01[o], s10[o], s11[o]);
+    return combine_phi(X[lds_swz(o)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))], s00[o], s01[o], s10[o], s11[o]);
   };
   fft_run<T, NT>(d.fi, ld_phi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
 }
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;
-  const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * ppw * Lj, d.tw_j, Lj);
+  const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
   const C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
   const int half = Lj / 2;
   auto ld = [&](int qq, int k, int) -> C {
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
       if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
     }
   };
-  fft_run<T, NT>(d.fj, ld, st, buf, buf + ppw * Lj, Lj, ppw, tw, true);
+  fft_run<T, NT>(d.fj, ld, st, buf, buf + lds_round(ppw * Lj), Lj, ppw, tw, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,7 +502,7 @@ static Batch pick_batch(int n, int want, size_t max_lds) {
   constexpr int cs = FftCap<T, kFftThreads>::elems, cl = FftCap<T, kFftThreadsLong>::elems;
   if (n > kFftThreadsLong * cl)
     throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
-  const int by_lds = std::max<int>(1, int(max_lds / (2 * size_t(n) * elem_bytes)));
+  const int by_lds = std::max<int>(1, int(max_lds / (2 * size_t(lds_round(n)) * elem_bytes)));
   const int target = std::max(1, std::min(want, by_lds));
   Batch b{};
   if (size_t(target) * n <= size_t(kFftThreads) * cs) {
@@ -512,7 +512,7 @@ static Batch pick_batch(int n, int want, size_t max_lds) {
     b.nt = kFftThreadsLong;
     b.batch = std::max(1, std::min(target, (kFftThreadsLong * cl) / n));
   }
-  if (2 * size_t(b.batch) * n * elem_bytes > 160 * 1024)
+  if (2 * size_t(lds_round(b.batch * n)) * elem_bytes > 160 * 1024)
     throw Error(-1, "FFT length " + std::to_string(n) + " does not fit in LDS");
   return b;
 }
@@ -575,8 +575,8 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     DevBuf tmp(sizeof(cplx<double>) * std::min(chunk, nslot) * per_slot);
     const Batch br = pick_batch<double>(Lj, 8, 80 * 1024);
     const Batch bc = pick_batch<double>(Li, 8, 80 * 1024);
-    const size_t lds_r = 2 * size_t(br.batch) * Lj * sizeof(cplx<double>);
-    const size_t lds_c = 2 * size_t(bc.batch) * Li * sizeof(cplx<double>);
+    const size_t lds_r = 2 * size_t(lds_round(br.batch * Lj)) * sizeof(cplx<double>);
+    const size_t lds_c = 2 * size_t(lds_round(bc.batch * Li)) * sizeof(cplx<double>);
     auto kr = br.nt == kFftThreads ? k_spec_rows<kFftThreads> : k_spec_rows<kFftThreadsLong>;
     auto kc = bc.nt == kFftThreads ? k_spec_cols<T, kFftThreads> : k_spec_cols<T, kFftThreadsLong>;
     allow_lds(kr, lds_r);
@@ -633,11 +633,11 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
 
 template <typename T>
 size_t GreenPlan<T>::lds_rows() const {
-  return (2 * size_t(dev_.ppw) + (twl_rows_ ? 1 : 0)) * Lj * sizeof(cplx<T>);
+  return (2 * size_t(lds_round(dev_.ppw * Lj)) + (twl_rows_ ? size_t(Lj) : 0)) * sizeof(cplx<T>);
 }
 template <typename T>
 size_t GreenPlan<T>::lds_cols() const {
-  return (2 * size_t(dev_.cpw) + (twl_cols_ ? 1 : 0)) * Li * sizeof(cplx<T>);
+  return (2 * size_t(lds_round(dev_.cpw * Li)) + (twl_cols_ ? size_t(Li) : 0)) * sizeof(cplx<T>);
 }
 
 // Calls f(rows_fwd, cols, rows_inv) with the kernel instantiations this plan
