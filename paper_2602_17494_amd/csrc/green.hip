@@ -328,13 +328,13 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   }
   __syncthreads();
   const C* res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
-  C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
+  C* S = d.S + static_cast<size_t>(b) * d.scol * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int k = d.fd_ppw.div(e), qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const C z = res[lds_swz(qq * Lj + k)];
     const C zn = res[lds_swz(qq * Lj + (k == 0 ? 0 : Lj - k))];
-    C* col = S + static_cast<size_t>(k) * d.rows_max;
+    C* col = S + static_cast<size_t>(k) * d.scol;
     if (ra < bx.ni) col[ra] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
     if (rb < bx.ni) col[rb] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
   }
@@ -400,22 +400,22 @@ __global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
   C* bufa = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
-  const int Li = d.Li, Lh = d.Lh, cpw = d.cpw, rows_max = d.rows_max;
+  const int Li = d.Li, Lh = d.Lh, cpw = d.cpw, scol = d.scol;
   C* bufb = bufa + lds_round(cpw * Li);
   const int k0 = blockIdx.y * cpw;
   const int ncol = min(cpw, Lh - k0);
   const C* tw = stage_twiddles<T, NT, TWL>(bufa + 2 * lds_round(cpw * Li), d.tw_i, Li);
-  C* S = d.S + static_cast<size_t>(b) * rows_max * Lh + static_cast<size_t>(k0) * rows_max;
+  C* S = d.S + static_cast<size_t>(b) * scol * Lh + static_cast<size_t>(k0) * scol;
   const size_t slot_sz = static_cast<size_t>(Li) * Lh, col0 = static_cast<size_t>(k0) * Li;
   const C* s00 = d.spec + static_cast<size_t>(bx.k00) * slot_sz + col0;
   const C* s01 = d.spec + static_cast<size_t>(bx.k01) * slot_sz + col0;
   const C* s10 = d.spec + static_cast<size_t>(bx.k10) * slot_sz + col0;
   const C* s11 = d.spec + static_cast<size_t>(bx.k11) * slot_sz + col0;
   auto ld_s = [&](int c, int r, int) -> C {
-    return (c < ncol && r < bx.ni) ? S[c * rows_max + r] : C{T(0), T(0)};
+    return (c < ncol && r < bx.ni) ? S[c * scol + r] : C{T(0), T(0)};
   };
   auto st_s = [&](int c, int r, C v) {
-    if (c < ncol && r < bx.ni) S[c * rows_max + r] = v;
+    if (c < ncol && r < bx.ni) S[c * scol + r] = v;
   };
   if constexpr (sizeof(T) == 4) {
   const int r0 = d.fi.radix[0], nbf0 = d.fi.nbf[0].d;
@@ -458,12 +458,12 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
-  const C* S = d.S + static_cast<size_t>(b) * d.rows_max * Lh;
+  const C* S = d.S + static_cast<size_t>(b) * d.scol * Lh;
   const int half = Lj / 2;
   auto ld = [&](int qq, int k, int) -> C {
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const int kk = k <= half ? k : Lj - k;
-    const C* col = S + static_cast<size_t>(kk) * d.rows_max;
+    const C* col = S + static_cast<size_t>(kk) * d.scol;
     const C a = ra < bx.ni ? col[ra] : C{T(0), T(0)};
     const C c = rb < bx.ni ? col[rb] : C{T(0), T(0)};
     return k <= half ? C{a.x - c.y, a.y + c.x} : C{a.x + c.y, c.x - a.y};
@@ -563,7 +563,11 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   tw_i_ = make_twiddles<T>(Li, s);
   tw_j_ = make_twiddles<T>(Lj, s);
   spec_.alloc(sizeof(cplx<T>) * nslot * size_t(Li) * Lh);
-  S_.alloc(sizeof(cplx<T>) * size_t(nbox) * rows_max * Lh);
+  // column stride of the half spectra: a multiple of 16 elements (128-byte
+  // chunks for float32) that is an odd multiple, so that the columns of a
+  // box do not all start on the same memory channel
+  const int scol = (rows_max + 31) / 32 * 32 + 16;
+  S_.alloc(sizeof(cplx<T>) * size_t(nbox) * scol * Lh);
 
   // build the window spectra in float64, a chunk of slots at a time
   {
@@ -608,7 +612,7 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   dev_.Li = Li;
   dev_.Lj = Lj;
   dev_.Lh = Lh;
-  dev_.rows_max = rows_max;
+  dev_.scol = scol;
   dev_.ppw = br.batch;
   dev_.cpw = bc.batch;
   dev_.fd_Li = make_fastdiv(Li);

@@ -55,7 +55,7 @@ template <typename T>
 struct GreenDev {
   int n2, n1;
   int Li, Lj, Lh;
-  int rows_max;
+  int scol;  // column stride of the half spectra S[box][k_j][row]
   int ppw, cpw;
   FastDiv fd_Li, fd_Lj, fd_ppw;
   T inv_h;
