@@ -343,7 +343,7 @@ __device__ __forceinline__ double dual_scale(double th, double t, double nn) {
 // Neighbour offsets are clamped to 0 where the grid ends, which makes the
 // corresponding forward difference of phi vanish and keeps every load inside
 // the frame; psi components there are set to 0 explicitly.
-constexpr int kRunY = 8;
+constexpr int kRunY = 2;
 
 static dim3 grid_runs(int n2, int n1, int nz) {
   return dim3((n1 + kBX - 1) / kBX, (n2 + kBY * kRunY - 1) / (kBY * kRunY), nz);
