@@ -400,7 +400,10 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
   T* nxt = dptr<T>(P.vb);
   T* zcur = dptr<T>(P.za);  // vecdiv of cur (0 for v = 0)
   T* znxt = dptr<T>(P.zb);
+  // z frames are written on the grown subdomains only; 0 elsewhere
   launch_fill<T>(zcur, 2 * sf.plane * sf.nsub, T(0), s);
+  launch_fill<T>(znxt, 2 * sf.plane * sf.nsub, T(0), s);
+  if (!P.plain) launch_fill<T>(dptr<T>(P.zw), 2 * sf.plane * sf.nsub, T(0), s);  // no zw when plain
   const double scale = std::sqrt(2.0 * double(gpl));
   KernelTimer* tm = &c->timer;
   const double px = P.ss.sub_px, esz = sizeof(T);

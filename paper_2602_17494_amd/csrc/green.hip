@@ -393,8 +393,9 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
 // workgroups (dealt round-robin to the eight XCDs) work on the same column
 // tile of neighbouring boxes; boxes of one subdomain column then share an
 // XCD and its L2 for the window spectra they have in common.
+// (at most 128 VGPRs, so that four 256-thread workgroups fit on a CU)
 template <typename T, int NT, bool TWL>
-__global__ __launch_bounds__(NT) void k_green_cols(GreenDev<T> d) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_green_cols(GreenDev<T> d) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* bufa = reinterpret_cast<C*>(smem_raw);

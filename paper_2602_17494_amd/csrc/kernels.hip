@@ -56,6 +56,7 @@ __global__ void k_fill(T* p, long long n, T v) {
 }
 template <typename T> void launch_fill(T* p, long long n, T v, hipStream_t s) {
   if (n <= 0) return;
+  if (!p) throw Error(-1, "internal: fill of an unallocated buffer");
   const int blocks = int(std::min<long long>(4096, (n + 255) / 256));
   hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(256), 0, s, p, n, v);
   TVS_LAUNCH_CHECK();
@@ -241,34 +242,64 @@ void launch_sub_theta_p(const SubFrames& sf, Grid g, const T* p, int planes, T* 
   TVS_LAUNCH_CHECK();
 }
 
-// z = vecdiv(E_m v) on the grown subdomain, 0 elsewhere in the frame
+// Element e of an array given by a 32-bit element offset (so the address is a
+// scalar base plus a 32-bit vector offset).
 template <typename T>
-__global__ void k_sub_vecdiv(SubFrames sf, Grid g, T inv_h, const T* __restrict__ v, T* __restrict__ z) {
-  const int q = blockIdx.x * kBX + threadIdx.x, r = blockIdx.y * kBY + threadIdx.y;
+__device__ __forceinline__ T ld32(const T* base, unsigned e) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * unsigned(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, unsigned e, T x) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * unsigned(sizeof(T))) = x;
+}
+
+// Per-subdomain stencil kernels give each thread a run of kRunY consecutive
+// rows of one frame column (a 64-wide wavefront spans one row segment, so
+// row quantities are uniform over it).
+constexpr int kRunY = 2;
+
+static dim3 grid_runs(int n2, int n1, int nz) {
+  return dim3((n1 + kBX - 1) / kBX, (n2 + kBY * kRunY - 1) / (kBY * kRunY), nz);
+}
+
+// z = vecdiv(E_m v) on the grown subdomain.  Only the grown subdomain is
+// written: the rest of a z frame is 0 from the start of the solve.  Row runs
+// as in the update kernels below, carrying v_xy and v_yy of the row above.
+template <typename T>
+__global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, Grid g, T inv_h,
+                                                        const T* __restrict__ v,
+                                                        T* __restrict__ z) {
+  const int q = blockIdx.x * kBX + threadIdx.x;
+  const int r0 = __builtin_amdgcn_readfirstlane((blockIdx.y * kBY + threadIdx.y) * kRunY);
   const SubDesc sd = sf.subs[blockIdx.z];
-  if (r >= sf.fr || q >= sf.fp) return;
-  const long long lo = (long long)r * sf.fp + q;
-  const T* vb = v + (long long)blockIdx.z * 4 * sf.plane;
-  T* zb = z + (long long)blockIdx.z * 2 * sf.plane;
-  if (r < sd.ai && q < sd.aj) {
-    const int gi = sd.i0 + r, gj = sd.j0 + q;
-    for (int k = 0; k < 2; ++k) {
-      const T* vx = vb + (2 * k) * sf.plane;
-      const T* vy = vb + (2 * k + 1) * sf.plane;
-      const T a = (gj == g.n1 - 1) ? T(0) : vx[lo];
-      const T am = (q > 0) ? vx[lo - 1] : T(0);
-      const T c = (gi == g.n2 - 1) ? T(0) : vy[lo];
-      const T cm = (r > 0) ? vy[lo - sf.fp] : T(0);
-      zb[k * sf.plane + lo] = ((a - am) + (c - cm)) * inv_h;
-    }
-  } else {
-    zb[lo] = T(0);
-    zb[sf.plane + lo] = T(0);
+  if (r0 >= sd.ai || q >= sd.aj) return;
+  const unsigned fp = sf.fp, pl = unsigned(sf.plane);
+  const size_t box = blockIdx.z;
+  const T* v0 = v + box * 4 * pl;
+  const T* v1 = v0 + pl;
+  const T* v2 = v1 + pl;
+  const T* v3 = v2 + pl;
+  T* z0 = z + box * 2 * pl;
+  T* z1 = z0 + pl;
+  const bool lastx = sd.j0 + q == g.n1 - 1;
+  const unsigned dl = q > 0 ? 1u : 0u;
+  unsigned o = unsigned(r0) * fp + unsigned(q);
+  T u1 = r0 > 0 ? ld32(v1, o - fp) : T(0), u3 = r0 > 0 ? ld32(v3, o - fp) : T(0);
+  const int rend = min(kRunY, sd.ai - r0);
+  int gi = sd.i0 + r0;
+  for (int rr = 0; rr < rend; ++rr, o += fp, ++gi) {
+    const bool lasty = gi == g.n2 - 1;
+    const T a0 = ld32(v0, o), l0 = ld32(v0, o - dl), a1 = ld32(v1, o);
+    const T a2 = ld32(v2, o), l2 = ld32(v2, o - dl), a3 = ld32(v3, o);
+    st32(z0, o, (((lastx ? T(0) : a0) - (q > 0 ? l0 : T(0))) + ((lasty ? T(0) : a1) - u1)) * inv_h);
+    st32(z1, o, (((lastx ? T(0) : a2) - (q > 0 ? l2 : T(0))) + ((lasty ? T(0) : a3) - u3)) * inv_h);
+    u1 = a1;
+    u3 = a3;
   }
 }
 template <typename T>
 void launch_sub_vecdiv(const SubFrames& sf, Grid g, T inv_h, const T* v, T* z, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid2d(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, inv_h, v, z);
+  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, inv_h, v, z);
   TVS_LAUNCH_CHECK();
 }
 
@@ -310,17 +341,6 @@ void launch_sub_omega(const SubFrames& sf, Grid g, T inv_h, const T* r, const T*
   TVS_LAUNCH_CHECK();
 }
 
-// Element e of an array given by a 32-bit element offset (so the address is a
-// scalar base plus a 32-bit vector offset).
-template <typename T>
-__device__ __forceinline__ T ld32(const T* base, unsigned e) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * unsigned(sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ void st32(T* base, unsigned e, T x) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * unsigned(sizeof(T))) = x;
-}
-
 // theta / (theta + t sqrt(nn)): FP32 uses the hardware square root (about
 // 1 ulp) and the hardware reciprocal refined by one Newton step; FP64 the
 // correctly rounded operations.
@@ -343,12 +363,6 @@ __device__ __forceinline__ double dual_scale(double th, double t, double nn) {
 // Neighbour offsets are clamped to 0 where the grid ends, which makes the
 // corresponding forward difference of phi vanish and keeps every load inside
 // the frame; psi components there are set to 0 explicitly.
-constexpr int kRunY = 2;
-
-static dim3 grid_runs(int n2, int n1, int nz) {
-  return dim3((n1 + kBX - 1) / kBX, (n2 + kBY * kRunY - 1) / (kBY * kRunY), nz);
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, Grid g, StepScalars<T> cs,
                                                          const T* __restrict__ v,
