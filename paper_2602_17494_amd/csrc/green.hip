@@ -340,14 +340,24 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   }
 }
 
-// Phi(ki) from X(ki), X(-ki) and the four window spectra at ki.
+// Phi(ki) from X(ki) = a + i b, X(-ki) = c + i d and the four window spectra:
+//   X K00 + conj(X(-ki)) K01 + X(-ki) K10 + conj(X) K11
+//     = a P + b Q + c R + d S,
+//   P = K00 + K11, Q = i (K00 - K11), R = K01 + K10, S = i (K10 - K01),
+// i.e. eight real multiply-adds once P, Q, R, S are formed.
 template <typename T>
-__device__ __forceinline__ cplx<T> combine_phi(cplx<T> x, cplx<T> xn, cplx<T> k00, cplx<T> k01,
-                                               cplx<T> k10, cplx<T> k11) {
-  cplx<T> acc = cmul(x, k00);
-  acc = cadd(acc, cmul(cconj(xn), k01));
-  acc = cadd(acc, cmul(xn, k10));
-  return cadd(acc, cmul(cconj(x), k11));
+struct PhiCoef {
+  cplx<T> p, q, r, s;
+};
+template <typename T>
+__device__ __forceinline__ PhiCoef<T> phi_coef(cplx<T> k00, cplx<T> k01, cplx<T> k10, cplx<T> k11) {
+  return PhiCoef<T>{cplx<T>{k00.x + k11.x, k00.y + k11.y}, cplx<T>{k11.y - k00.y, k00.x - k11.x},
+                    cplx<T>{k01.x + k10.x, k01.y + k10.y}, cplx<T>{k01.y - k10.y, k10.x - k01.x}};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> combine_phi(cplx<T> x, cplx<T> xn, const PhiCoef<T>& k) {
+  return cplx<T>{x.x * k.p.x + x.y * k.q.x + xn.x * k.r.x + xn.y * k.s.x,
+                 x.x * k.p.y + x.y * k.q.y + xn.x * k.r.y + xn.y * k.s.y};
 }
 
 // Column pass with the window spectra of the first inverse pass (radix R,
@@ -359,6 +369,7 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
                                                 bool act, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   const int Li = d.Li, cpw = d.cpw, nbf = d.fi.nbf[0].d;
+  // raw values only: combining them here would wait for the loads
   C k[4][R];
 #pragma unroll
   for (int t = 0; t < R; ++t) {
@@ -373,8 +384,8 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       const int ki = j + t * nbf;
-      v[t] = combine_phi(X[lds_swz(c * Li + ki)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))], k[0][t], k[1][t],
-                         k[2][t], k[3][t]);
+      v[t] = combine_phi(X[lds_swz(c * Li + ki)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))],
+                         phi_coef(k[0][t], k[1][t], k[2][t], k[3][t]));
     }
     butterfly<R, T>(v, true);
 #pragma unroll
@@ -443,7 +454,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   auto ld_phi = [&](int c, int ki, int) -> C {
     if (c >= ncol) return C{T(0), T(0)};
     const int o = c * Li + ki;
-    return combine_phi(X[lds_swz(o)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))], s00[o], s01[o], s10[o], s11[o]);
+    return combine_phi(X[lds_swz(o)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))],
+                       phi_coef(s00[o], s01[o], s10[o], s11[o]));
   };
   fft_run<T, NT>(d.fi, ld_phi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
 }
