@@ -258,23 +258,48 @@ __device__ __forceinline__ void st32(T* base, unsigned e, T x) {
 // row quantities are uniform over it).
 constexpr int kRunY = 2;
 
-static dim3 grid_runs(int n2, int n1, int nz) {
-  return dim3((n1 + kBX - 1) / kBX, (n2 + kBY * kRunY - 1) / (kBY * kRunY), nz);
+// Tiles of kBX columns x kBY * kRunY rows of the nz frames are numbered rows
+// fastest, then columns, then frames.  Workgroups are dealt round-robin to
+// the 8 XCDs, so workgroup w takes tile (w mod 8) * per + w / 8 (per = tiles
+// per XCD, the grid is 8 * per): each XCD then works through a contiguous
+// range of tiles, and tiles that share halo rows run on the same XCD, close
+// in time, and find those rows in its L2.
+struct RunTiles {
+  int ncx, nry, n;
+};
+static RunTiles run_tiles(int n2, int n1, int nz) {
+  RunTiles t{(n1 + kBX - 1) / kBX, (n2 + kBY * kRunY - 1) / (kBY * kRunY), 0};
+  t.n = t.ncx * t.nry * nz;
+  return t;
+}
+static dim3 grid_runs(const RunTiles& t) { return dim3(8 * ((t.n + 7) / 8)); }
+// This thread's frame column q, first row r0 (wavefront-uniform) and frame;
+// false for the workgroups past the last tile.
+__device__ __forceinline__ bool run_tile(const RunTiles& t, int& q, int& r0, int& box) {
+  const int per = int(gridDim.x) / 8;
+  const int w = blockIdx.x;
+  const int tile = (w & 7) * per + (w >> 3);
+  if (tile >= t.n) return false;
+  const int ry = tile % t.nry, rest = tile / t.nry;
+  box = rest / t.ncx;
+  q = (rest - box * t.ncx) * kBX + threadIdx.x;
+  r0 = __builtin_amdgcn_readfirstlane((ry * kBY + int(threadIdx.y)) * kRunY);
+  return true;
 }
 
 // z = vecdiv(E_m v) on the grown subdomain.  Only the grown subdomain is
 // written: the rest of a z frame is 0 from the start of the solve.  Row runs
 // as in the update kernels below, carrying v_xy and v_yy of the row above.
 template <typename T>
-__global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, Grid g, T inv_h,
+__global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, RunTiles rt, Grid g, T inv_h,
                                                         const T* __restrict__ v,
                                                         T* __restrict__ z) {
-  const int q = blockIdx.x * kBX + threadIdx.x;
-  const int r0 = __builtin_amdgcn_readfirstlane((blockIdx.y * kBY + threadIdx.y) * kRunY);
-  const SubDesc sd = sf.subs[blockIdx.z];
+  int q, r0, bz;
+  if (!run_tile(rt, q, r0, bz)) return;
+  const SubDesc sd = sf.subs[bz];
   if (r0 >= sd.ai || q >= sd.aj) return;
   const unsigned fp = sf.fp, pl = unsigned(sf.plane);
-  const size_t box = blockIdx.z;
+  const size_t box = bz;
   const T* v0 = v + box * 4 * pl;
   const T* v1 = v0 + pl;
   const T* v2 = v1 + pl;
@@ -299,7 +324,8 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, Grid g, T
 }
 template <typename T>
 void launch_sub_vecdiv(const SubFrames& sf, Grid g, T inv_h, const T* v, T* z, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, inv_h, v, z);
+  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
+  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, inv_h, v, z);
   TVS_LAUNCH_CHECK();
 }
 
@@ -364,18 +390,18 @@ __device__ __forceinline__ double dual_scale(double th, double t, double nn) {
 // corresponding forward difference of phi vanish and keeps every load inside
 // the frame; psi components there are set to 0 explicitly.
 template <typename T>
-__global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, Grid g, StepScalars<T> cs,
+__global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, RunTiles rt, Grid g, StepScalars<T> cs,
                                                          const T* __restrict__ v,
                                                          const T* __restrict__ z,
                                                          const T* __restrict__ phi,
                                                          const T* __restrict__ omega,
                                                          T* __restrict__ v_out) {
-  const int q = blockIdx.x * kBX + threadIdx.x;
-  const int r0 = __builtin_amdgcn_readfirstlane((blockIdx.y * kBY + threadIdx.y) * kRunY);
-  const SubDesc sd = sf.subs[blockIdx.z];
+  int q, r0, bz;
+  if (!run_tile(rt, q, r0, bz)) return;
+  const SubDesc sd = sf.subs[bz];
   if (r0 >= sd.si || q >= sd.sj) return;
   const unsigned fp = sf.fp, pl = unsigned(sf.plane);
-  const size_t box = blockIdx.z;
+  const size_t box = bz;
   const T* v0 = v + box * 4 * pl;
   const T* v1 = v0 + pl;
   const T* v2 = v1 + pl;
@@ -429,7 +455,8 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, Grid g, 
 template <typename T>
 void launch_sub_update1(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* z,
                         const T* phi, const T* omega, T* v_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, c, v, z, phi, omega, v_out);
+  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
+  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, z, phi, omega, v_out);
   TVS_LAUNCH_CHECK();
 }
 
@@ -553,16 +580,16 @@ void launch_sub2_prologue(const SubFrames& sf, Grid g, T inv_h, const T* p, cons
 // frame support, or on the grid's last row/column, are selected to 0; their
 // loads use clamped offsets inside the frame.
 template <typename T>
-__global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, Grid g, StepScalars<T> cs,
+__global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, RunTiles rt, Grid g, StepScalars<T> cs,
                                                          const T* __restrict__ v,
                                                          const T* __restrict__ bfr,
                                                          T* __restrict__ v_out) {
-  const int q = blockIdx.x * kBX + threadIdx.x;
-  const int r0 = __builtin_amdgcn_readfirstlane((blockIdx.y * kBY + threadIdx.y) * kRunY);
-  const SubDesc sd = sf.subs[blockIdx.z];
+  int q, r0, bz;
+  if (!run_tile(rt, q, r0, bz)) return;
+  const SubDesc sd = sf.subs[bz];
   if (r0 >= sd.si || q >= sd.sj) return;
   const unsigned fp = sf.fp, pl = unsigned(sf.plane);
-  const size_t box = blockIdx.z;
+  const size_t box = bz;
   const T* vx = v + box * 2 * pl;
   const T* vy = vx + pl;
   const T* bb = bfr + box * pl;
@@ -613,7 +640,8 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, Grid g, 
 template <typename T>
 void launch_sub2_update(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* b,
                         T* v_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(sf.fr, sf.fp, sf.nsub), dim3(kBX, kBY), 0, s, sf, g, c, v, b, v_out);
+  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
+  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, b, v_out);
   TVS_LAUNCH_CHECK();
 }
 
