@@ -59,8 +59,9 @@ enum {
   TVS_OK = 0,
   TVS_EINVAL = -1,    /* shape, parameter or layout out of range */
   TVS_ENOMEM = -2,    /* device allocation failed */
-  TVS_EHIP = -3,      /* a HIP runtime call or kernel launch failed */
-  TVS_ENONFINITE = -4 /* an FP64 reduction found NaN or Inf */
+  TVS_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+  TVS_ENONFINITE = -4, /* an FP64 reduction found NaN or Inf */
+  TVS_EBUSY = -5       /* a job's result was asked for before it finished */
 };
 
 typedef enum { TVS_F32 = 0, TVS_F64 = 1 } tvs_dtype;
@@ -181,6 +182,51 @@ int tvs_timing_reset(tvs_ctx* ctx);
 int tvs_timing_count(tvs_ctx* ctx);
 int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* launches, double* ms,
                    double* bytes);
+
+/* Jobs: one image's Step 1 + Step 2 solve (the same problem and the same
+ * computation as tvs_schwarz_solve, whose results it reproduces bit for bit)
+ * with its own device state, resident between calls: the problem's plans,
+ * the dual variables of every subdomain, a copy of d0, tau and d.  A job is
+ * advanced one Schwarz sweep (Algorithm 2) at a time, so that a caller can
+ * interleave the sweeps of many jobs, admit new ones between sweeps and
+ * retire finished ones (continuous batching).
+ *   tvs_job_footprint  bytes of device memory a job of this shape needs (its
+ *                      own state, plus the Green-function table the context
+ *                      keeps once per grid size), computed on the host
+ *   tvs_job_create     validate as tvs_schwarz_solve, allocate and build the
+ *                      job's state, copy d0 (device pointer, N2 x N1; the
+ *                      caller may reuse it on return) and run the Step-1
+ *                      set-up on `stream`; the call waits for that work
+ *   tvs_batch_sweep    advance each of the n jobs (of this context) by one
+ *                      sweep of its current step, in order, on `stream`; the
+ *                      sweep that completes Step 1 also computes tau and its
+ *                      statistics (which waits for the stream) and sets up
+ *                      Step 2; the one that completes Step 2 computes d.  A
+ *                      finished job is left as it is.  Jobs sharing nothing,
+ *                      the order of the list does not change any result.
+ *   tvs_job_status     step 1 or 2 (3 when finished), sweeps done in it,
+ *                      done = 1 when finished; any pointer may be NULL
+ *   tvs_job_result     copy d (N2 x N1) and tau (2 x (N2+1) x (N1+1)) into
+ *                      the caller's device buffers (either may be NULL) on
+ *                      `stream`, and the two steps' statistics into
+ *                      stats[2] (may be NULL); TVS_EBUSY before the job has
+ *                      finished
+ *   tvs_job_bytes      device bytes held by the job (0 for NULL)
+ *   tvs_job_destroy    wait for the device, free the job (NULL is a no-op)
+ * The calls on one job must not overlap; jobs of one context share its kernel
+ * timer only. */
+typedef struct tvs_job tvs_job;
+int tvs_job_footprint(int N2, int N1, tvs_dtype dtype, const tvs_layout* layout,
+                      const tvs_iters* iters, size_t* bytes);
+int tvs_job_create(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dtype,
+                   const tvs_params* params, const tvs_layout* layout, const tvs_iters* iters,
+                   void* stream, tvs_job** out);
+int tvs_batch_sweep(tvs_ctx* ctx, tvs_job* const* jobs, int n, void* stream);
+int tvs_job_status(const tvs_job* job, int* step, int* sweeps_done, int* done);
+int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_stats* stats,
+                   void* stream);
+size_t tvs_job_bytes(const tvs_job* job);
+int tvs_job_destroy(tvs_job* job);
 
 #ifdef __cplusplus
 }

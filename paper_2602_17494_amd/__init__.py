@@ -1,7 +1,7 @@
 """TV-Stokes denoising with overlapping Schwarz domain decomposition on AMD
 MI355X: Python binding of the HIP library libtvs (see include/tvs.h)."""
-from .tvs import (Context, Params, Layout, Iters, Stats, TvsError, make_params, make_layout,
-                  make_iters, TVS_IRV1, TVS_IRV2, load)
+from .tvs import (Context, Job, Params, Layout, Iters, Stats, TvsError, job_footprint, make_params,
+                  make_layout, make_iters, TVS_EBUSY, TVS_IRV1, TVS_IRV2, load)
 
-__all__ = ["Context", "Params", "Layout", "Iters", "Stats", "TvsError", "make_params",
-           "make_layout", "make_iters", "TVS_IRV1", "TVS_IRV2", "load"]
+__all__ = ["Context", "Job", "Params", "Layout", "Iters", "Stats", "TvsError", "job_footprint",
+           "make_params", "make_layout", "make_iters", "TVS_EBUSY", "TVS_IRV1", "TVS_IRV2", "load"]

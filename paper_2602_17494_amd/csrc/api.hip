@@ -96,10 +96,38 @@ void build_theta_tables(SubSet& ss, hipStream_t s) {
   ss.sf.thx_f = ss.sf.thy_f + ny;
 }
 
+// frame shape shared by all subdomains of a set (host side)
+void finish_subs(SubSet& ss, int fr, int fp) {
+  ss.sf.nsub = int(ss.subs.size());
+  ss.sf.fr = fr;
+  ss.sf.fp = align_pitch(fp);
+  ss.sf.plane = (long long)fr * ss.sf.fp;
+  // byte offsets inside one subdomain's four planes are 32-bit in the kernels
+  if (4 * 8 * ss.sf.plane >= (1LL << 32)) throw Error(TVS_EINVAL, "layout: subdomain frame too large");
+  ss.sf.ay = ss.ay;
+  ss.sf.ax = ss.ax;
+}
+
+// the descriptors and theta tables on the device
+void upload_subs(SubSet& ss, hipStream_t s) {
+  ss.subs_d.alloc(sizeof(SubDesc) * ss.subs.size());
+  TVS_HIP(hipMemcpyAsync(ss.subs_d.p, ss.subs.data(), sizeof(SubDesc) * ss.subs.size(),
+                         hipMemcpyHostToDevice, s));
+  ss.sf.subs = ss.subs_d.as<SubDesc>();
+  build_theta_tables(ss, s);
+}
+
+// device bytes of upload_subs
+size_t subs_device_bytes(const SubSet& ss) {
+  const size_t ny = size_t(ss.ay.m) * ss.sf.fr, nx = size_t(ss.ax.m) * ss.sf.fp;
+  return sizeof(SubDesc) * ss.subs.size() + (ny + nx) * (sizeof(double) + sizeof(float));
+}
+
 // Step 1 subdomains on Omega-tilde: s = the subdomain, a = grown by one
 // row/column, b = grown by two (clipped at the grid)
-void build_subs1(SubSet& ss, int n2, int n1, hipStream_t s) {
+void plan_subs1(SubSet& ss, int n2, int n1) {
   ss.subs.clear();
+  ss.sub_px = 0;
   int fr = 0, fp = 0;
   for (int a = 0; a < ss.ay.m; ++a)
     for (int b = 0; b < ss.ax.m; ++b) {
@@ -119,24 +147,13 @@ void build_subs1(SubSet& ss, int n2, int n1, hipStream_t s) {
       ss.sub_px += double(d.si) * d.sj;
       ss.subs.push_back(d);
     }
-  ss.subs_d.alloc(sizeof(SubDesc) * ss.subs.size());
-  TVS_HIP(hipMemcpyAsync(ss.subs_d.p, ss.subs.data(), sizeof(SubDesc) * ss.subs.size(),
-                         hipMemcpyHostToDevice, s));
-  ss.sf.subs = ss.subs_d.as<SubDesc>();
-  ss.sf.nsub = int(ss.subs.size());
-  ss.sf.fr = fr;
-  ss.sf.fp = align_pitch(fp);
-  ss.sf.plane = (long long)fr * ss.sf.fp;
-  // byte offsets inside one subdomain's four planes are 32-bit in the kernels
-  if (4 * 8 * ss.sf.plane >= (1LL << 32)) throw Error(TVS_EINVAL, "layout: subdomain frame too large");
-  ss.sf.ay = ss.ay;
-  ss.sf.ax = ss.ax;
-  build_theta_tables(ss, s);
+  finish_subs(ss, fr, fp);
 }
 
 // Step 2 subdomains: the Step-1 ones cut to Omega; a = grown by one
-void build_subs2(SubSet& ss, int N2, int N1, hipStream_t s) {
+void plan_subs2(SubSet& ss, int N2, int N1) {
   ss.subs.clear();
+  ss.sub_px = 0;
   int fr = 0, fp = 0;
   for (int a = 0; a < ss.ay.m; ++a)
     for (int b = 0; b < ss.ax.m; ++b) {
@@ -157,19 +174,16 @@ void build_subs2(SubSet& ss, int N2, int N1, hipStream_t s) {
       ss.sub_px += double(d.si) * d.sj;
       ss.subs.push_back(d);
     }
-  ss.subs_d.alloc(sizeof(SubDesc) * ss.subs.size());
-  TVS_HIP(hipMemcpyAsync(ss.subs_d.p, ss.subs.data(), sizeof(SubDesc) * ss.subs.size(),
-                         hipMemcpyHostToDevice, s));
-  ss.sf.subs = ss.subs_d.as<SubDesc>();
-  ss.sf.nsub = int(ss.subs.size());
-  ss.sf.fr = fr;
-  ss.sf.fp = align_pitch(fp);
-  ss.sf.plane = (long long)fr * ss.sf.fp;
-  // byte offsets inside one subdomain's four planes are 32-bit in the kernels
-  if (4 * 8 * ss.sf.plane >= (1LL << 32)) throw Error(TVS_EINVAL, "layout: subdomain frame too large");
-  ss.sf.ay = ss.ay;
-  ss.sf.ax = ss.ax;
-  build_theta_tables(ss, s);
+  finish_subs(ss, fr, fp);
+}
+
+void build_subs1(SubSet& ss, int n2, int n1, hipStream_t s) {
+  plan_subs1(ss, n2, n1);
+  upload_subs(ss, s);
+}
+void build_subs2(SubSet& ss, int N2, int N1, hipStream_t s) {
+  plan_subs2(ss, N2, N1);
+  upload_subs(ss, s);
 }
 
 template <typename T>
@@ -183,7 +197,7 @@ struct Step1Problem {
   size_t bytes() const {
     size_t b = tau0.bytes + f1.bytes + r.bytes + zg.bytes + phig.bytes + p.bytes + va.bytes +
                vb.bytes + vt.bytes + za.bytes + zb.bytes + zw.bytes + phi.bytes + omega.bytes +
-               global->bytes();
+               global->bytes() + ss.subs_d.bytes + ss.theta_d.bytes;
     if (local) b += local->bytes();
     return b;
   }
@@ -195,7 +209,8 @@ struct Step2Problem {
   SubSet ss;
   DevBuf f2, p, u, xi, va, vb, b;
   size_t bytes() const {
-    return f2.bytes + p.bytes + u.bytes + xi.bytes + va.bytes + vb.bytes + b.bytes;
+    return f2.bytes + p.bytes + u.bytes + xi.bytes + va.bytes + vb.bytes + b.bytes + ss.subs_d.bytes +
+           ss.theta_d.bytes;
   }
 };
 
@@ -281,12 +296,9 @@ double alpha_hat_of(const tvs_layout* l) {
 }
 
 template <typename T>
-Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
+std::unique_ptr<Step1Problem<T>> make_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l,
+                                            hipStream_t s) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
-  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x};
-  auto& mp = s1map<T>(c);
-  auto it = mp.find(key);
-  if (it != mp.end()) return *it->second;
   auto P = std::make_unique<Step1Problem<T>>();
   const int n2 = N2 + 1, n1 = N1 + 1;
   P->g = Grid{n2, n1, h};
@@ -319,18 +331,12 @@ Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layou
   P->za.alloc(2 * fpb);
   P->zb.alloc(2 * fpb);
   P->phi.alloc(fpb);
-  auto& ref = *P;
-  mp[key] = std::move(P);
-  return ref;
+  return P;
 }
 
 template <typename T>
-Step2Problem<T>& get_step2(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
+std::unique_ptr<Step2Problem<T>> make_step2(int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
-  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x};
-  auto& mp = s2map<T>(c);
-  auto it = mp.find(key);
-  if (it != mp.end()) return *it->second;
   auto P = std::make_unique<Step2Problem<T>>();
   P->g = Grid{N2, N1, h};
   P->ss.ay = make_axis(N2 + 1, l->M2, l->s_y, "M2");
@@ -345,8 +351,29 @@ Step2Problem<T>& get_step2(tvs_ctx* c, int N2, int N1, double h, const tvs_layou
   P->va.alloc(2 * fpb);
   P->vb.alloc(2 * fpb);
   P->b.alloc(fpb);
-  auto& ref = *P;
-  mp[key] = std::move(P);
+  return P;
+}
+
+// problems cached in the context by shape (the one-shot calls)
+template <typename T>
+Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
+  if (!l) throw Error(TVS_EINVAL, "layout is NULL");
+  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x};
+  auto& mp = s1map<T>(c);
+  auto it = mp.find(key);
+  if (it != mp.end()) return *it->second;
+  auto& ref = *(mp[key] = make_step1<T>(c, N2, N1, h, l, s));
+  return ref;
+}
+
+template <typename T>
+Step2Problem<T>& get_step2(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
+  if (!l) throw Error(TVS_EINVAL, "layout is NULL");
+  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x};
+  auto& mp = s2map<T>(c);
+  auto it = mp.find(key);
+  if (it != mp.end()) return *it->second;
+  auto& ref = *(mp[key] = make_step2<T>(N2, N1, h, l, s));
   return ref;
 }
 
@@ -369,70 +396,100 @@ double read1(const double* d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Step 1: Algorithm 2 on Omega-tilde with the inner loop of Algorithm 5
+// Step 1: Algorithm 2 on Omega-tilde with the inner loop of Algorithm 5, as a
+// resumable run: begin() (a1), sweep() (a2-a4: one Schwarz sweep), end() (a5
+// and the statistics).  run_step1 chains them; a job calls sweep() once per
+// batch sweep.  e holds the FP64 energy of every sweep, then the gap.
 // ---------------------------------------------------------------------------
 template <typename T>
-void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, const tvs_layout* l,
-               const tvs_iters* its, T* tau_out, tvs_stats* st, hipStream_t s) {
-  Step1Problem<T>& P = get_step1<T>(c, N2, N1, prm->h, l, s);
-  const Grid g = P.g;
-  const SubFrames& sf = P.ss.sf;
-  const T inv_h = T(1.0 / prm->h);
-  StepScalars<T> cs{T(prm->t), inv_h, T(prm->delta), T(prm->alpha), T(alpha_hat_of(l))};
-  const Frame gf = global_frame(g);
-  const Frame f2p = sub_frame(sf, 2), f1p = sub_frame(sf, 1);
-  const long long gpl = (long long)g.n2 * g.n1;
-  Partials part = partials(c);
-  double* e = scal(c, size_t(its->sweeps) + 3);
+struct Step1Run {
+  Step1Problem<T>* P = nullptr;
+  const T* d0 = nullptr;
+  int N2 = 0, N1 = 0;
+  tvs_params prm{};
+  tvs_iters its{};
+  StepScalars<T> cs{};
+  Partials part{};
+  double* e = nullptr;
+  KernelTimer* tm = nullptr;
+  T *cur = nullptr, *nxt = nullptr, *zcur = nullptr, *znxt = nullptr;
+  int n = 0, done = 0;
+  bool finished = false;
 
-  // a1: tau_0 and f = delta^{-1} P_K tau_0
-  launch_tau0<T>(d0, N2, N1, inv_h, dptr<T>(P.tau0), s);
-  P.global->apply_div(dptr<T>(P.tau0), gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s);
-  launch_f1<T>(dptr<T>(P.tau0), dptr<T>(P.phig), g, inv_h, T(1.0 / prm->delta), dptr<T>(P.f1), s);
-  launch_fill<T>(dptr<T>(P.p), 4 * gpl, T(0), s);
-  launch_fill<T>(dptr<T>(P.va), 4 * sf.plane * sf.nsub, T(0), s);
-  launch_fill<T>(dptr<T>(P.vb), 4 * sf.plane * sf.nsub, T(0), s);
-  GreenPlan<T>& lp = P.plain ? *P.global : *P.local;
-  // in the single-domain case omega = f (theta = 1), staged into the frame layout
-  if (P.plain) launch_sub_theta_p<T>(sf, g, dptr<T>(P.f1), 2, dptr<T>(P.omega), s);
-  const T* omega = dptr<T>(P.omega);
-  T* cur = dptr<T>(P.va);
-  T* nxt = dptr<T>(P.vb);
-  T* zcur = dptr<T>(P.za);  // vecdiv of cur (0 for v = 0)
-  T* znxt = dptr<T>(P.zb);
-  // z frames are written on the grown subdomains only; 0 elsewhere
-  launch_fill<T>(zcur, 2 * sf.plane * sf.nsub, T(0), s);
-  launch_fill<T>(znxt, 2 * sf.plane * sf.nsub, T(0), s);
-  if (!P.plain) launch_fill<T>(dptr<T>(P.zw), 2 * sf.plane * sf.nsub, T(0), s);  // no zw when plain
-  const double scale = std::sqrt(2.0 * double(gpl));
-  KernelTimer* tm = &c->timer;
-  const double px = P.ss.sub_px, esz = sizeof(T);
-  const char* ltag = P.plain ? "s1_plain" : "s1_local";
-  int done = 0;
-  for (int n = 0; n < its->sweeps; ++n) {
+  Step1Run(Step1Problem<T>& prob, const T* d0_, int N2_, int N1_, const tvs_params* p, const tvs_layout* l,
+           const tvs_iters* it, Partials pt, double* e_, KernelTimer* t)
+      : P(&prob), d0(d0_), N2(N2_), N1(N1_), prm(*p), its(*it), part(pt), e(e_), tm(t) {
+    const T inv_h = T(1.0 / prm.h);
+    cs = StepScalars<T>{T(prm.t), inv_h, T(prm.delta), T(prm.alpha), T(alpha_hat_of(l))};
+  }
+  GreenPlan<T>& lp() { return P->plain ? *P->global : *P->local; }
+  double scale() const { return std::sqrt(2.0 * double(P->g.n2) * P->g.n1); }
+
+  void begin(hipStream_t s) {
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
+    const long long gpl = (long long)g.n2 * g.n1;
+    // a1: tau_0 and f = delta^{-1} P_K tau_0
+    launch_tau0<T>(d0, N2, N1, cs.inv_h, dptr<T>(P->tau0), s);
+    P->global->apply_div(dptr<T>(P->tau0), global_frame(g), dptr<T>(P->phig), Frame{0, 0, g.n1}, s);
+    launch_f1<T>(dptr<T>(P->tau0), dptr<T>(P->phig), g, cs.inv_h, T(1.0 / prm.delta), dptr<T>(P->f1), s);
+    launch_fill<T>(dptr<T>(P->p), 4 * gpl, T(0), s);
+    launch_fill<T>(dptr<T>(P->va), 4 * sf.plane * sf.nsub, T(0), s);
+    launch_fill<T>(dptr<T>(P->vb), 4 * sf.plane * sf.nsub, T(0), s);
+    // in the single-domain case omega = f (theta = 1), staged into the frame layout
+    if (P->plain) launch_sub_theta_p<T>(sf, g, dptr<T>(P->f1), 2, dptr<T>(P->omega), s);
+    cur = dptr<T>(P->va);
+    nxt = dptr<T>(P->vb);
+    zcur = dptr<T>(P->za);  // vecdiv of cur (0 for v = 0)
+    znxt = dptr<T>(P->zb);
+    // z frames are written on the grown subdomains only; 0 elsewhere
+    launch_fill<T>(zcur, 2 * sf.plane * sf.nsub, T(0), s);
+    launch_fill<T>(znxt, 2 * sf.plane * sf.nsub, T(0), s);
+    if (!P->plain) launch_fill<T>(dptr<T>(P->zw), 2 * sf.plane * sf.nsub, T(0), s);  // no zw when plain
+    n = done = 0;
+    finished = false;
+  }
+
+  // One sweep; false once the run has no sweep left (count reached, or the
+  // stopping residual fell below the tolerance, which reads it back).
+  bool sweep(hipStream_t s) {
+    if (finished) return false;
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
+    const T inv_h = cs.inv_h;
+    const Frame gf = global_frame(g);
+    const Frame f2p = sub_frame(sf, 2), f1p = sub_frame(sf, 1);
+    const long long gpl = (long long)g.n2 * g.n1;
+    const double px = P->ss.sub_px, esz = sizeof(T);
+    const char* ltag = P->plain ? "s1_plain" : "s1_local";
     // a2: r^n = f - P_K vecdiv p^n (global, once per sweep) and D(p^n)
-    launch_global_vecdiv<T>(dptr<T>(P.p), g, inv_h, dptr<T>(P.zg), s);
-    P.global->apply_div(dptr<T>(P.zg), gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s, tm, "s1_global");
-    launch_residual<T>(dptr<T>(P.f1), dptr<T>(P.zg), dptr<T>(P.phig), g, inv_h, dptr<T>(P.r), part, e + n, s);
-    if (its->tol > 0 && n >= 1) {
+    launch_global_vecdiv<T>(dptr<T>(P->p), g, inv_h, dptr<T>(P->zg), s);
+    P->global->apply_div(dptr<T>(P->zg), gf, dptr<T>(P->phig), Frame{0, 0, g.n1}, s, tm, "s1_global");
+    launch_residual<T>(dptr<T>(P->f1), dptr<T>(P->zg), dptr<T>(P->phig), g, inv_h, dptr<T>(P->r), part, e + n, s);
+    if (its.tol > 0 && n >= 1) {
       double hv[2];
       TVS_HIP(hipMemcpyAsync(hv, e + n - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
       TVS_HIP(hipStreamSynchronize(s));
-      if (residual_of(hv[0], hv[1], scale) < its->tol) break;
+      if (residual_of(hv[0], hv[1], scale()) < its.tol) {
+        finished = true;
+        return false;
+      }
     }
-    if (!P.plain) {
+    const T* omega = dptr<T>(P->omega);
+    GreenPlan<T>& plan = lp();
+    if (!P->plain) {
       // omega_m = R_{m,+} r^n + LP_m(vecdiv(theta_m p^n))
-      launch_sub_theta_p<T>(sf, g, dptr<T>(P.p), 4, dptr<T>(P.vt), s);
-      launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P.vt), dptr<T>(P.zw), s);
-      lp.apply_div(dptr<T>(P.zw), f2p, dptr<T>(P.phi), f1p, s, tm, ltag);
-      launch_sub_omega<T>(sf, g, inv_h, dptr<T>(P.r), dptr<T>(P.zw), dptr<T>(P.phi), dptr<T>(P.omega), s);
+      launch_sub_theta_p<T>(sf, g, dptr<T>(P->p), 4, dptr<T>(P->vt), s);
+      launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P->vt), dptr<T>(P->zw), s);
+      plan.apply_div(dptr<T>(P->zw), f2p, dptr<T>(P->phi), f1p, s, tm, ltag);
+      launch_sub_omega<T>(sf, g, inv_h, dptr<T>(P->r), dptr<T>(P->zw), dptr<T>(P->phi), dptr<T>(P->omega), s);
     }
     // a3: inner iterations, warm-started from the previous sweep's q_m:
     // phi = Delta^+ div z on the Green box, the update of v, z' = vecdiv v'
-    for (int nu = 0; nu < its->inner; ++nu) {
-      lp.apply_div(zcur, f2p, dptr<T>(P.phi), f1p, s, tm, ltag);
+    for (int nu = 0; nu < its.inner; ++nu) {
+      plan.apply_div(zcur, f2p, dptr<T>(P->phi), f1p, s, tm, ltag);
       KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
-        launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P.phi), omega, nxt, s);
+        launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P->phi), omega, nxt, s);
       });
       KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
                         [&] { launch_sub_vecdiv<T>(sf, g, inv_h, nxt, znxt, s); });
@@ -441,104 +498,169 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
     }
     // a4: p^{n+1} = (1 - ahat) p^n + ahat sum_m q_m
     KernelTimer::time(tm, "s1_combine", 4 * esz * (2.0 * gpl + px), s,
-                      [&] { launch_combine<T>(sf, g, 4, cs.ahat, cur, dptr<T>(P.p), s); });
+                      [&] { launch_combine<T>(sf, g, 4, cs.ahat, cur, dptr<T>(P->p), s); });
     ++done;
+    ++n;
+    if (n >= its.sweeps) finished = true;
+    return !finished;
   }
-  // a5: tau = delta (f - P_K vecdiv p), D(p^S) and the gap
-  launch_global_vecdiv<T>(dptr<T>(P.p), g, inv_h, dptr<T>(P.zg), s);
-  P.global->apply_div(dptr<T>(P.zg), gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s);
-  launch_residual<T>(dptr<T>(P.f1), dptr<T>(P.zg), dptr<T>(P.phig), g, inv_h, dptr<T>(P.r), part, e + done, s);
-  launch_scale<T>(dptr<T>(P.r), 2 * gpl, T(prm->delta), tau_out, s);
-  // tau already lies in K; projecting it once more is the identity in exact
-  // arithmetic and removes the small divergence left by rounding, which the
-  // IRV2 row integral of tau_2 would otherwise accumulate across the image
-  P.global->apply_div(tau_out, gf, dptr<T>(P.phig), Frame{0, 0, g.n1}, s, tm, "s1_global");
-  launch_f1<T>(tau_out, dptr<T>(P.phig), g, inv_h, T(1), tau_out, s);
-  if (st) {
-    launch_gap_tfs<T>(tau_out, dptr<T>(P.p), g, inv_h, part, e + its->sweeps + 1, s);
-    std::vector<double> hv(size_t(its->sweeps) + 2);
-    TVS_HIP(hipMemcpyAsync(hv.data(), e, sizeof(double) * hv.size(), hipMemcpyDeviceToHost, s));
-    TVS_HIP(hipStreamSynchronize(s));
-    st->sweeps_done = done;
-    st->energy = hv[done];
-    st->residual = done >= 1 ? residual_of(hv[done - 1], hv[done], scale) : 0.0;
-    st->gap = hv[its->sweeps + 1];
-    if (!std::isfinite(st->energy) || !std::isfinite(st->gap))
-      throw Error(TVS_ENONFINITE, "step 1: non-finite energy or gap");
+
+  void end(T* tau_out, tvs_stats* st, hipStream_t s) {
+    const Grid g = P->g;
+    const T inv_h = cs.inv_h;
+    const Frame gf = global_frame(g);
+    const long long gpl = (long long)g.n2 * g.n1;
+    // a5: tau = delta (f - P_K vecdiv p), D(p^S) and the gap
+    launch_global_vecdiv<T>(dptr<T>(P->p), g, inv_h, dptr<T>(P->zg), s);
+    P->global->apply_div(dptr<T>(P->zg), gf, dptr<T>(P->phig), Frame{0, 0, g.n1}, s);
+    launch_residual<T>(dptr<T>(P->f1), dptr<T>(P->zg), dptr<T>(P->phig), g, inv_h, dptr<T>(P->r), part, e + done, s);
+    launch_scale<T>(dptr<T>(P->r), 2 * gpl, T(prm.delta), tau_out, s);
+    // tau already lies in K; projecting it once more is the identity in exact
+    // arithmetic and removes the small divergence left by rounding, which the
+    // IRV2 row integral of tau_2 would otherwise accumulate across the image
+    P->global->apply_div(tau_out, gf, dptr<T>(P->phig), Frame{0, 0, g.n1}, s, tm, "s1_global");
+    launch_f1<T>(tau_out, dptr<T>(P->phig), g, inv_h, T(1), tau_out, s);
+    if (st) {
+      launch_gap_tfs<T>(tau_out, dptr<T>(P->p), g, inv_h, part, e + its.sweeps + 1, s);
+      std::vector<double> hv(size_t(its.sweeps) + 2);
+      TVS_HIP(hipMemcpyAsync(hv.data(), e, sizeof(double) * hv.size(), hipMemcpyDeviceToHost, s));
+      TVS_HIP(hipStreamSynchronize(s));
+      st->sweeps_done = done;
+      st->energy = hv[done];
+      st->residual = done >= 1 ? residual_of(hv[done - 1], hv[done], scale()) : 0.0;
+      st->gap = hv[its.sweeps + 1];
+      if (!std::isfinite(st->energy) || !std::isfinite(st->gap))
+        throw Error(TVS_ENONFINITE, "step 1: non-finite energy or gap");
+    }
   }
+};
+
+template <typename T>
+void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, const tvs_layout* l,
+               const tvs_iters* its, T* tau_out, tvs_stats* st, hipStream_t s) {
+  Step1Problem<T>& P = get_step1<T>(c, N2, N1, prm->h, l, s);
+  Step1Run<T> run(P, d0, N2, N1, prm, l, its, partials(c), scal(c, size_t(its->sweeps) + 3), &c->timer);
+  run.begin(s);
+  while (run.sweep(s)) {
+  }
+  run.end(tau_out, st, s);
 }
 
 // ---------------------------------------------------------------------------
-// Step 2: Algorithm 2 on Omega with the inner loop of Algorithm 3
+// Step 2: Algorithm 2 on Omega with the inner loop of Algorithm 3, resumable
+// in the same way: begin() (a6 and the set-up), sweep() (a7-a9), end() (the
+// image and the statistics).
 // ---------------------------------------------------------------------------
 template <typename T>
-void run_step2(tvs_ctx* c, const T* d0, const T* tau, int N2, int N1, const tvs_params* prm,
-               const tvs_layout* l, const tvs_iters* its, T* d_out, tvs_stats* st, hipStream_t s) {
-  Step2Problem<T>& P = get_step2<T>(c, N2, N1, prm->h, l, s);
-  const Grid g = P.g;
-  const SubFrames& sf = P.ss.sf;
-  const T inv_h = T(1.0 / prm->h);
-  StepScalars<T> cs{T(prm->t), inv_h, T(prm->delta), T(prm->alpha), T(alpha_hat_of(l))};
-  const long long gpl = (long long)N2 * N1;
-  Partials part = partials(c);
-  double* e = scal(c, size_t(its->sweeps) + 3);
-  const bool irv1 = prm->variant == TVS_IRV1;
+struct Step2Run {
+  Step2Problem<T>* P = nullptr;
+  const T* d0 = nullptr;
+  int N2 = 0, N1 = 0;
+  tvs_params prm{};
+  tvs_iters its{};
+  StepScalars<T> cs{};
+  Partials part{};
+  double* e = nullptr;
+  KernelTimer* tm = nullptr;
+  T *cur = nullptr, *nxt = nullptr;
+  int n = 0, done = 0;
+  bool finished = false;
 
-  // a6: the bridge from tau to the Step-2 data
-  if (irv1) {
-    launch_xi<T>(tau, N2, N1, T(prm->eps), dptr<T>(P.xi), s);
-    launch_irv1_data<T>(d0, dptr<T>(P.xi), g, inv_h, T(prm->alpha), dptr<T>(P.f2), s);
-  } else {
-    launch_bridge_irv2<T>(tau, d0, N2, N1, T(prm->h), T(prm->alpha), dptr<T>(P.f2), s);
+  Step2Run(Step2Problem<T>& prob, const T* d0_, int N2_, int N1_, const tvs_params* p, const tvs_layout* l,
+           const tvs_iters* it, Partials pt, double* e_, KernelTimer* t)
+      : P(&prob), d0(d0_), N2(N2_), N1(N1_), prm(*p), its(*it), part(pt), e(e_), tm(t) {
+    const T inv_h = T(1.0 / prm.h);
+    cs = StepScalars<T>{T(prm.t), inv_h, T(prm.delta), T(prm.alpha), T(alpha_hat_of(l))};
   }
-  launch_fill<T>(dptr<T>(P.p), 2 * gpl, T(0), s);
-  launch_fill<T>(dptr<T>(P.va), 2 * sf.plane * sf.nsub, T(0), s);
-  launch_fill<T>(dptr<T>(P.vb), 2 * sf.plane * sf.nsub, T(0), s);
-  T* cur = dptr<T>(P.va);
-  T* nxt = dptr<T>(P.vb);
-  const double scale = std::sqrt(double(gpl));
-  KernelTimer* tm = &c->timer;
-  const double px = P.ss.sub_px, esz = sizeof(T);
-  int done = 0;
-  for (int n = 0; n < its->sweeps; ++n) {
-    launch_energy_rof<T>(dptr<T>(P.p), dptr<T>(P.f2), g, inv_h, part, e + n, s);
-    if (its->tol > 0 && n >= 1) {
+  bool irv1() const { return prm.variant == TVS_IRV1; }
+  double scale() const { return std::sqrt(double(N2) * N1); }
+
+  void begin(const T* tau, hipStream_t s) {
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
+    const long long gpl = (long long)N2 * N1;
+    // a6: the bridge from tau to the Step-2 data
+    if (irv1()) {
+      launch_xi<T>(tau, N2, N1, T(prm.eps), dptr<T>(P->xi), s);
+      launch_irv1_data<T>(d0, dptr<T>(P->xi), g, cs.inv_h, T(prm.alpha), dptr<T>(P->f2), s);
+    } else {
+      launch_bridge_irv2<T>(tau, d0, N2, N1, T(prm.h), T(prm.alpha), dptr<T>(P->f2), s);
+    }
+    launch_fill<T>(dptr<T>(P->p), 2 * gpl, T(0), s);
+    launch_fill<T>(dptr<T>(P->va), 2 * sf.plane * sf.nsub, T(0), s);
+    launch_fill<T>(dptr<T>(P->vb), 2 * sf.plane * sf.nsub, T(0), s);
+    cur = dptr<T>(P->va);
+    nxt = dptr<T>(P->vb);
+    n = done = 0;
+    finished = false;
+  }
+
+  bool sweep(hipStream_t s) {
+    if (finished) return false;
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
+    const long long gpl = (long long)N2 * N1;
+    const double px = P->ss.sub_px, esz = sizeof(T);
+    launch_energy_rof<T>(dptr<T>(P->p), dptr<T>(P->f2), g, cs.inv_h, part, e + n, s);
+    if (its.tol > 0 && n >= 1) {
       double hv[2];
       TVS_HIP(hipMemcpyAsync(hv, e + n - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
       TVS_HIP(hipStreamSynchronize(s));
-      if (residual_of(hv[0], hv[1], scale) < its->tol) break;
+      if (residual_of(hv[0], hv[1], scale()) < its.tol) {
+        finished = true;
+        return false;
+      }
     }
     // a7: b_m = div((1 - theta_m) p^n) - f near the subdomain
-    launch_sub2_prologue<T>(sf, g, inv_h, dptr<T>(P.p), dptr<T>(P.f2), dptr<T>(P.b), s);
+    launch_sub2_prologue<T>(sf, g, cs.inv_h, dptr<T>(P->p), dptr<T>(P->f2), dptr<T>(P->b), s);
     // a8: inner iterations
-    for (int nu = 0; nu < its->inner; ++nu) {
+    for (int nu = 0; nu < its.inner; ++nu) {
       KernelTimer::time(tm, "s2_update", 5 * esz * px, s,
-                        [&] { launch_sub2_update<T>(sf, g, cs, cur, dptr<T>(P.b), nxt, s); });
+                        [&] { launch_sub2_update<T>(sf, g, cs, cur, dptr<T>(P->b), nxt, s); });
       std::swap(cur, nxt);
     }
     // a9: combine
     KernelTimer::time(tm, "s2_combine", 2 * esz * (2.0 * gpl + px), s,
-                      [&] { launch_combine<T>(sf, g, 2, cs.ahat, cur, dptr<T>(P.p), s); });
+                      [&] { launch_combine<T>(sf, g, 2, cs.ahat, cur, dptr<T>(P->p), s); });
     ++done;
+    ++n;
+    if (n >= its.sweeps) finished = true;
+    return !finished;
   }
-  launch_energy_rof<T>(dptr<T>(P.p), dptr<T>(P.f2), g, inv_h, part, e + done, s);
-  if (irv1)
-    launch_irv1_image<T>(d0, dptr<T>(P.p), dptr<T>(P.xi), g, inv_h, T(1.0 / prm->alpha), d_out, s);
-  else
-    launch_irv2_image<T>(d0, dptr<T>(P.p), g, inv_h, T(1.0 / prm->alpha), d_out, s);
-  if (st) {
-    launch_primal_rof<T>(dptr<T>(P.p), dptr<T>(P.f2), g, inv_h, T(1.0 / prm->alpha), dptr<T>(P.u), s);
-    launch_gap_rof<T>(dptr<T>(P.u), dptr<T>(P.p), g, inv_h, part, e + its->sweeps + 1, s);
-    std::vector<double> hv(size_t(its->sweeps) + 2);
-    TVS_HIP(hipMemcpyAsync(hv.data(), e, sizeof(double) * hv.size(), hipMemcpyDeviceToHost, s));
-    TVS_HIP(hipStreamSynchronize(s));
-    st->sweeps_done = done;
-    st->energy = hv[done];
-    st->residual = done >= 1 ? residual_of(hv[done - 1], hv[done], scale) : 0.0;
-    st->gap = hv[its->sweeps + 1];
-    if (!std::isfinite(st->energy) || !std::isfinite(st->gap))
-      throw Error(TVS_ENONFINITE, "step 2: non-finite energy or gap");
+
+  void end(T* d_out, tvs_stats* st, hipStream_t s) {
+    const Grid g = P->g;
+    const T inv_h = cs.inv_h;
+    launch_energy_rof<T>(dptr<T>(P->p), dptr<T>(P->f2), g, inv_h, part, e + done, s);
+    if (irv1())
+      launch_irv1_image<T>(d0, dptr<T>(P->p), dptr<T>(P->xi), g, inv_h, T(1.0 / prm.alpha), d_out, s);
+    else
+      launch_irv2_image<T>(d0, dptr<T>(P->p), g, inv_h, T(1.0 / prm.alpha), d_out, s);
+    if (st) {
+      launch_primal_rof<T>(dptr<T>(P->p), dptr<T>(P->f2), g, inv_h, T(1.0 / prm.alpha), dptr<T>(P->u), s);
+      launch_gap_rof<T>(dptr<T>(P->u), dptr<T>(P->p), g, inv_h, part, e + its.sweeps + 1, s);
+      std::vector<double> hv(size_t(its.sweeps) + 2);
+      TVS_HIP(hipMemcpyAsync(hv.data(), e, sizeof(double) * hv.size(), hipMemcpyDeviceToHost, s));
+      TVS_HIP(hipStreamSynchronize(s));
+      st->sweeps_done = done;
+      st->energy = hv[done];
+      st->residual = done >= 1 ? residual_of(hv[done - 1], hv[done], scale()) : 0.0;
+      st->gap = hv[its.sweeps + 1];
+      if (!std::isfinite(st->energy) || !std::isfinite(st->gap))
+        throw Error(TVS_ENONFINITE, "step 2: non-finite energy or gap");
+    }
   }
+};
+
+template <typename T>
+void run_step2(tvs_ctx* c, const T* d0, const T* tau, int N2, int N1, const tvs_params* prm,
+               const tvs_layout* l, const tvs_iters* its, T* d_out, tvs_stats* st, hipStream_t s) {
+  Step2Problem<T>& P = get_step2<T>(c, N2, N1, prm->h, l, s);
+  Step2Run<T> run(P, d0, N2, N1, prm, l, its, partials(c), scal(c, size_t(its->sweeps) + 3), &c->timer);
+  run.begin(tau, s);
+  while (run.sweep(s)) {
+  }
+  run.end(d_out, st, s);
 }
 
 template <typename T>
@@ -587,10 +709,128 @@ struct DeviceGuard {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Jobs: one image's solve with its own resident state (problems, dual
+// variables, d0/tau/d), advanced one Schwarz sweep at a time.  A job runs the
+// same launches in the same order as the one-shot calls, so its results are
+// bit-identical to theirs.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct JobState {
+  DevBuf d0, tau, dout, part, e1, e2;
+  std::unique_ptr<Step1Problem<T>> p1;
+  std::unique_ptr<Step2Problem<T>> p2;
+  std::unique_ptr<Step1Run<T>> r1;
+  std::unique_ptr<Step2Run<T>> r2;
+  size_t bytes() const {
+    return d0.bytes + tau.bytes + dout.bytes + part.bytes + e1.bytes + e2.bytes + p1->bytes() +
+           p2->bytes();
+  }
+};
+
+// bytes of a job's own device state, computed on the host (the same
+// allocations as JobState, make_step1 and make_step2)
+template <typename T>
+size_t job_bytes_estimate(int N2, int N1, const tvs_layout* l, int sweeps) {
+  const size_t esz = sizeof(T);
+  const int n2 = N2 + 1, n1 = N1 + 1;
+  const bool plain = l->M2 == 1 && l->M1 == 1;
+  SubSet s1;
+  s1.ay = make_axis(n2, l->M2, l->s_y, "M2");
+  s1.ax = make_axis(n1, l->M1, l->s_x, "M1");
+  plan_subs1(s1, n2, n1);
+  size_t b = 13 * size_t(n2) * n1 * esz + size_t(plain ? 15 : 21) * size_t(s1.sf.plane) * s1.sf.nsub * esz +
+             subs_device_bytes(s1) + GreenPlan<T>::footprint({{0, 0, n2, n1}});
+  if (!plain) {
+    std::vector<std::array<int, 4>> boxes;
+    for (auto& d : s1.subs) boxes.push_back({d.i0, d.j0, d.bi, d.bj});
+    b += GreenPlan<T>::footprint(boxes);
+  }
+  SubSet s2;
+  s2.ay = make_axis(n2, l->M2, l->s_y, "M2");
+  s2.ax = make_axis(n1, l->M1, l->s_x, "M1");
+  plan_subs2(s2, N2, N1);
+  b += 6 * size_t(N2) * N1 * esz + 5 * size_t(s2.sf.plane) * s2.sf.nsub * esz + subs_device_bytes(s2);
+  b += (2 * size_t(N2) * N1 + 2 * size_t(n2) * n1) * esz + sizeof(double) * 1024 +
+       2 * sizeof(double) * (size_t(sweeps) + 3);
+  return b;
+}
+
 }  // namespace
 }  // namespace tvs
 
+struct tvs_job {
+  tvs_ctx* ctx = nullptr;
+  tvs_dtype dtype = TVS_F32;
+  int N2 = 0, N1 = 0;
+  tvs_params prm{};
+  tvs_layout lay{};
+  tvs_iters its{};
+  int step = 1;  // 1, 2, or 3 when finished
+  tvs_stats st[2]{};
+  std::unique_ptr<tvs::JobState<float>> f;
+  std::unique_ptr<tvs::JobState<double>> d;
+};
+
 using namespace tvs;
+
+namespace {
+
+template <typename T>
+JobState<T>& job_state(tvs_job* j);
+template <>
+JobState<float>& job_state<float>(tvs_job* j) { return *j->f; }
+template <>
+JobState<double>& job_state<double>(tvs_job* j) { return *j->d; }
+
+template <typename T>
+void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s) {
+  auto st = std::make_unique<JobState<T>>();
+  const int N2 = j->N2, N1 = j->N1;
+  const size_t esz = sizeof(T);
+  st->d0.alloc(esz * size_t(N2) * N1);
+  st->tau.alloc(2 * esz * size_t(N2 + 1) * (N1 + 1));
+  st->dout.alloc(esz * size_t(N2) * N1);
+  st->part.alloc(sizeof(double) * 1024);
+  st->e1.alloc(sizeof(double) * (size_t(j->its.sweeps) + 3));
+  st->e2.alloc(sizeof(double) * (size_t(j->its.sweeps) + 3));
+  st->p1 = make_step1<T>(c, N2, N1, j->prm.h, &j->lay, s);
+  st->p2 = make_step2<T>(N2, N1, j->prm.h, &j->lay, s);
+  TVS_HIP(hipMemcpyAsync(st->d0.p, d0, esz * size_t(N2) * N1, hipMemcpyDeviceToDevice, s));
+  st->r1 = std::make_unique<Step1Run<T>>(*st->p1, st->d0.template as<T>(), N2, N1, &j->prm, &j->lay, &j->its,
+                                         Partials{st->part.template as<double>(), 1024}, st->e1.template as<double>(), &c->timer);
+  st->r1->begin(s);
+  // later calls may come on another stream
+  TVS_HIP(hipStreamSynchronize(s));
+  if constexpr (sizeof(T) == 4)
+    j->f = std::move(st);
+  else
+    j->d = std::move(st);
+}
+
+// one sweep of the job's current step; the step's end (and the next step's
+// begin) follow the sweep that completes it
+template <typename T>
+void job_sweep(tvs_ctx* c, tvs_job* j, hipStream_t s) {
+  JobState<T>& st = job_state<T>(j);
+  if (j->step == 1) {
+    if (!st.r1->sweep(s)) {
+      st.r1->end(st.tau.template as<T>(), &j->st[0], s);
+      st.r2 = std::make_unique<Step2Run<T>>(*st.p2, st.d0.template as<T>(), j->N2, j->N1, &j->prm, &j->lay,
+                                            &j->its, Partials{st.part.template as<double>(), 1024},
+                                            st.e2.template as<double>(), &c->timer);
+      st.r2->begin(st.tau.template as<T>(), s);
+      j->step = 2;
+    }
+  } else if (j->step == 2) {
+    if (!st.r2->sweep(s)) {
+      st.r2->end(st.dout.template as<T>(), &j->st[1], s);
+      j->step = 3;
+    }
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -776,6 +1016,121 @@ int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dty
       run_project<double>(ctx, static_cast<const double*>(u_in), n2, n1, h, static_cast<double*>(u_out), s);
     else
       throw Error(TVS_EINVAL, "unknown dtype");
+  });
+}
+
+int tvs_job_footprint(int N2, int N1, tvs_dtype dtype, const tvs_layout* layout, const tvs_iters* iters,
+                      size_t* bytes) {
+  return guarded([&] {
+    if (!layout || !iters || !bytes) throw Error(TVS_EINVAL, "NULL argument");
+    if (N2 < 2 || N1 < 2) throw Error(TVS_EINVAL, "image must be at least 2 x 2");
+    check_iters(iters);
+    // the job's own state plus the Green-function table of its grid, which the
+    // context holds once per grid size
+    const size_t table = sizeof(double) * size_t(N2 + 2) * (N1 + 2);
+    if (dtype == TVS_F32)
+      *bytes = job_bytes_estimate<float>(N2, N1, layout, iters->sweeps) + table;
+    else if (dtype == TVS_F64)
+      *bytes = job_bytes_estimate<double>(N2, N1, layout, iters->sweeps) + table;
+    else
+      throw Error(TVS_EINVAL, "unknown dtype");
+  });
+}
+
+int tvs_job_create(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dtype,
+                   const tvs_params* params, const tvs_layout* layout, const tvs_iters* iters,
+                   void* stream, tvs_job** out) {
+  return guarded([&] {
+    if (!ctx || !d0 || !layout || !out) throw Error(TVS_EINVAL, "NULL argument");
+    *out = nullptr;
+    check_params(params, N2, N1);
+    check_iters(iters);
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto j = std::make_unique<tvs_job>();
+    j->ctx = ctx;
+    j->dtype = dtype;
+    j->N2 = N2;
+    j->N1 = N1;
+    j->prm = *params;
+    j->lay = *layout;
+    j->its = *iters;
+    if (dtype == TVS_F32)
+      job_create<float>(ctx, j.get(), static_cast<const float*>(d0), s);
+    else if (dtype == TVS_F64)
+      job_create<double>(ctx, j.get(), static_cast<const double*>(d0), s);
+    else
+      throw Error(TVS_EINVAL, "unknown dtype");
+    *out = j.release();
+  });
+}
+
+int tvs_batch_sweep(tvs_ctx* ctx, tvs_job* const* jobs, int n, void* stream) {
+  return guarded([&] {
+    if (!ctx || (n > 0 && !jobs) || n < 0) throw Error(TVS_EINVAL, "bad job list");
+    for (int i = 0; i < n; ++i)
+      if (!jobs[i] || jobs[i]->ctx != ctx) throw Error(TVS_EINVAL, "job missing or of another context");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+      tvs_job* j = jobs[i];
+      if (j->dtype == TVS_F32)
+        job_sweep<float>(ctx, j, s);
+      else
+        job_sweep<double>(ctx, j, s);
+    }
+  });
+}
+
+int tvs_job_status(const tvs_job* job, int* step, int* sweeps_done, int* done) {
+  return guarded([&] {
+    if (!job) throw Error(TVS_EINVAL, "NULL job");
+    int sw = 0;
+    if (job->dtype == TVS_F32) {
+      sw = job->step == 1 ? job->f->r1->done : job->f->r2->done;
+    } else {
+      sw = job->step == 1 ? job->d->r1->done : job->d->r2->done;
+    }
+    if (step) *step = job->step;
+    if (sweeps_done) *sweeps_done = sw;
+    if (done) *done = job->step == 3 ? 1 : 0;
+  });
+}
+
+int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_stats* stats,
+                   void* stream) {
+  return guarded([&] {
+    if (!ctx || !job || job->ctx != ctx) throw Error(TVS_EINVAL, "bad job");
+    if (job->step != 3) throw Error(TVS_EBUSY, "the job has not finished");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t esz = job->dtype == TVS_F64 ? sizeof(double) : sizeof(float);
+    const DevBuf& dd = job->dtype == TVS_F64 ? job->d->dout : job->f->dout;
+    const DevBuf& tt = job->dtype == TVS_F64 ? job->d->tau : job->f->tau;
+    if (d_out)
+      TVS_HIP(hipMemcpyAsync(d_out, dd.p, esz * size_t(job->N2) * job->N1, hipMemcpyDeviceToDevice, s));
+    if (tau_out)
+      TVS_HIP(hipMemcpyAsync(tau_out, tt.p, 2 * esz * size_t(job->N2 + 1) * (job->N1 + 1),
+                             hipMemcpyDeviceToDevice, s));
+    if (stats) {
+      stats[0] = job->st[0];
+      stats[1] = job->st[1];
+    }
+  });
+}
+
+size_t tvs_job_bytes(const tvs_job* job) {
+  if (!job) return 0;
+  return job->dtype == TVS_F64 ? job->d->bytes() : job->f->bytes();
+}
+
+int tvs_job_destroy(tvs_job* job) {
+  return guarded([&] {
+    if (!job) return;
+    DeviceGuard dg(job->ctx->device);
+    // launches of the job may still be queued on the caller's stream
+    TVS_HIP(hipDeviceSynchronize());
+    delete job;
   });
 }
 

@@ -1,6 +1,8 @@
 // Image-method Neumann inverse Laplacian on boxes (see green.hpp).
 #include "green.hpp"
 
+#include <set>
+
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -698,6 +700,25 @@ void GreenPlan<T>::for_each_variant(F&& f) const {
 template <typename T>
 size_t GreenPlan<T>::bytes() const {
   return spec_.bytes + S_.bytes + boxes_d_.bytes + tw_i_.bytes + tw_j_.bytes;
+}
+template <typename T>
+size_t GreenPlan<T>::footprint(const std::vector<std::array<int, 4>>& boxes) {
+  int rmax = 0, cmax = 0;
+  std::set<SlotKey> keys;
+  for (auto& bx : boxes) {
+    rmax = std::max(rmax, bx[2]);
+    cmax = std::max(cmax, bx[3]);
+    const int i0 = bx[0], j0 = bx[1], ni = bx[2], nj = bx[3];
+    keys.insert({0, 0, -1, -1});
+    keys.insert({0, 2 * j0 + nj, -1, nj - 1});
+    keys.insert({2 * i0 + ni, 0, ni - 1, -1});
+    keys.insert({2 * i0 + ni, 2 * j0 + nj, ni - 1, nj - 1});
+  }
+  const size_t li = size_t(smooth_even_at_least(2 * rmax - 1));
+  const size_t lj = size_t(smooth_even_at_least(2 * cmax - 1)), lh = lj / 2 + 1;
+  const size_t scol = size_t((rmax + 31) / 32 * 32 + 16);
+  return sizeof(cplx<T>) * (keys.size() * li * lh + boxes.size() * scol * lh + li + lj) +
+         sizeof(GreenBox) * boxes.size();
 }
 
 // Algorithmic bytes: the row passes read the source field (2 planes) of

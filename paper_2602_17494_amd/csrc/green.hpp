@@ -85,6 +85,8 @@ class GreenPlan {
   int rows_max, cols_max;
   size_t nslot = 0;
   size_t bytes() const;
+  // bytes() of a plan for these boxes, computed on the host without building it
+  static size_t footprint(const std::vector<std::array<int, 4>>& boxes);
 
  private:
   GreenDev<T> dev_{};

@@ -1,0 +1,116 @@
+"""Continuous batching of TV-Stokes denoise requests on one GPU.
+
+Each request is a job of the HIP library (tvs_job_*): its dual variables and
+plans stay resident on the device between Schwarz sweeps.  The server loop
+admits waiting requests in arrival order while the sum of the admitted jobs'
+device footprints stays within a byte budget, advances every live job by one
+sweep per round (one tvs_batch_sweep call), and retires the jobs that have
+finished, so that requests arriving while others run join the next round and
+their work interleaves on the device with the running ones.  A job computes
+exactly what a one-shot tvs_schwarz_solve of its image computes.
+"""
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from .tvs import Context, Job, job_footprint
+
+
+@dataclass
+class Request:
+    rid: int
+    d0: torch.Tensor          # GPU image, float32 or float64
+    params: object            # tvs_params
+    layout: object            # tvs_layout
+    iters: object             # tvs_iters
+    arrival: float = 0.0      # seconds after the start of the run
+    footprint: int = 0
+
+
+@dataclass
+class Result:
+    rid: int
+    d: torch.Tensor
+    tau: torch.Tensor
+    stats: list
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+@dataclass
+class Server:
+    ctx: Context
+    budget: int                       # device bytes the live jobs may hold
+    queue: list = field(default_factory=list)
+    live: list = field(default_factory=list)   # (request, job, admitted time)
+    in_use: int = 0
+    peak_in_use: int = 0
+    rounds: int = 0
+
+    def submit(self, req: Request):
+        req.footprint = job_footprint(tuple(req.d0.shape), req.d0.dtype, req.layout, req.iters)
+        if req.footprint > self.budget:
+            raise ValueError(f"request {req.rid} needs {req.footprint} bytes, over the budget")
+        self.queue.append(req)
+
+    def _admit(self, now):
+        while self.queue and self.in_use + self.queue[0].footprint <= self.budget:
+            req = self.queue.pop(0)
+            job = self.ctx.job(req.d0, req.params, req.layout, req.iters)
+            self.in_use += req.footprint
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.live.append((req, job, now))
+
+    def round(self, now_fn):
+        """Admit what fits, advance every live job by one sweep, retire the
+        finished ones; returns their results."""
+        self._admit(now_fn())
+        if not self.live:
+            return []
+        self.ctx.batch_sweep([job for _, job, _ in self.live])
+        self.rounds += 1
+        torch.cuda.current_stream(self.ctx.device).synchronize()
+        out, keep = [], []
+        for req, job, adm in self.live:
+            if job.done:
+                d, tau, st = job.result()
+                torch.cuda.current_stream(self.ctx.device).synchronize()
+                out.append(Result(req.rid, d, tau, st, req.arrival, adm, now_fn()))
+                job.close()
+                self.in_use -= req.footprint
+            else:
+                keep.append((req, job, adm))
+        self.live = keep
+        return out
+
+
+def serve(ctx, requests, budget, clock=time.perf_counter):
+    """Run `requests` (with arrival offsets in seconds) through a server
+    with the given byte budget in real time; returns the results in
+    completion order and the server (for its counters)."""
+    pending = sorted(requests, key=lambda r: r.arrival)
+    srv = Server(ctx, budget)
+    t0 = clock()
+    now = lambda: clock() - t0
+    done = []
+    while pending or srv.queue or srv.live:
+        while pending and pending[0].arrival <= now():
+            srv.submit(pending.pop(0))
+        if not srv.queue and not srv.live:
+            time.sleep(max(0.0, min(0.01, pending[0].arrival - now())))
+            continue
+        done.extend(srv.round(now))
+    return done, srv
+
+
+def latency_summary(results):
+    lat = np.array([r.latency for r in results])
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            "mean": float(lat.mean()), "n": int(lat.size)}

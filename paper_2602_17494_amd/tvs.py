@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtvs.so")
 
 TVS_F32, TVS_F64 = 0, 1
+TVS_EBUSY = -5
 TVS_IRV2, TVS_IRV1 = 0, 1
 
 
@@ -86,13 +87,30 @@ def load():
     lib.tvs_timing_get.argtypes = [vp, ci, ctypes.c_char_p, ci, ctypes.POINTER(ctypes.c_longlong),
                                    ctypes.POINTER(cd), ctypes.POINTER(cd)]
     lib.tvs_timing_get.restype = ci
+    sz = ctypes.c_size_t
+    lib.tvs_job_footprint.argtypes = [ci, ci, ci, L, I, ctypes.POINTER(sz)]
+    lib.tvs_job_footprint.restype = ci
+    lib.tvs_job_create.argtypes = [vp, vp, ci, ci, ci, P, L, I, vp, ctypes.POINTER(vp)]
+    lib.tvs_job_create.restype = ci
+    lib.tvs_batch_sweep.argtypes = [vp, ctypes.POINTER(vp), ci, vp]
+    lib.tvs_batch_sweep.restype = ci
+    lib.tvs_job_status.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    lib.tvs_job_status.restype = ci
+    lib.tvs_job_result.argtypes = [vp, vp, vp, vp, S, vp]
+    lib.tvs_job_result.restype = ci
+    lib.tvs_job_bytes.argtypes = [vp]
+    lib.tvs_job_bytes.restype = sz
+    lib.tvs_job_destroy.argtypes = [vp]
+    lib.tvs_job_destroy.restype = ci
     _lib = lib
     return lib
 
 
 EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_bytes", "tvs_step1",
             "tvs_step2", "tvs_schwarz_solve", "tvs_project_div_free", "tvs_timing_enable",
-            "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get"]
+            "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get", "tvs_job_footprint",
+            "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
+            "tvs_job_bytes", "tvs_job_destroy"]
 
 
 def _check(code):
@@ -225,6 +243,21 @@ class Context:
             out[buf.value.decode()] = (la.value, ms.value, by.value)
         return out
 
+    # -- jobs (resident state, one Schwarz sweep per batch call) -------------
+    def job(self, d0, params, layout, iters):
+        """Create a job solving d0 (a GPU tensor, copied) with both steps."""
+        n2, n1 = d0.shape
+        h = ctypes.c_void_p()
+        _check(load().tvs_job_create(self._h, _dev(d0, (n2, n1)), n2, n1, _dtype_code(d0),
+                                     ctypes.byref(params), ctypes.byref(layout), ctypes.byref(iters),
+                                     _stream(d0.device), ctypes.byref(h)))
+        return Job(self, h, n2, n1, d0.dtype)
+
+    def batch_sweep(self, jobs):
+        """Advance every job in the list by one sweep of its current step."""
+        arr = (ctypes.c_void_p * max(1, len(jobs)))(*[j._h.value for j in jobs])
+        _check(load().tvs_batch_sweep(self._h, arr, len(jobs), _stream(self.device)))
+
     def project_div_free(self, u, h=1.0, out=None):
         _, n2, n1 = u.shape
         if out is None:
@@ -233,3 +266,62 @@ class Context:
                                            float(h), _dev(out, (2, n2, n1), u.dtype),
                                            _stream(u.device)))
         return out
+
+
+def job_footprint(shape, dtype, layout, iters):
+    """Device bytes a job of this image shape needs (host-side estimate that
+    equals the job's allocation plus its grid's Green-function table)."""
+    n2, n1 = shape
+    code = TVS_F32 if dtype == torch.float32 else TVS_F64 if dtype == torch.float64 else None
+    if code is None:
+        raise TypeError("dtype must be float32 or float64")
+    out = ctypes.c_size_t()
+    _check(load().tvs_job_footprint(int(n2), int(n1), code, ctypes.byref(layout), ctypes.byref(iters),
+                                    ctypes.byref(out)))
+    return int(out.value)
+
+
+class Job:
+    """One image's solve with resident device state (see tvs_job_* in tvs.h)."""
+
+    def __init__(self, ctx, handle, n2, n1, dtype):
+        self.ctx, self._h, self.shape, self.dtype = ctx, handle, (n2, n1), dtype
+
+    def status(self):
+        """(step, sweeps done in it, finished)"""
+        st, sw, dn = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().tvs_job_status(self._h, ctypes.byref(st), ctypes.byref(sw), ctypes.byref(dn)))
+        return st.value, sw.value, bool(dn.value)
+
+    @property
+    def done(self):
+        return self.status()[2]
+
+    def bytes(self):
+        return int(load().tvs_job_bytes(self._h))
+
+    def result(self, d_out=None, tau_out=None):
+        """(d, tau, [stats step 1, stats step 2]); raises TvsError (TVS_EBUSY)
+        before the job has finished."""
+        n2, n1 = self.shape
+        dev = self.ctx.device
+        if d_out is None:
+            d_out = torch.empty((n2, n1), dtype=self.dtype, device=dev)
+        if tau_out is None:
+            tau_out = torch.empty((2, n2 + 1, n1 + 1), dtype=self.dtype, device=dev)
+        st = (Stats * 2)()
+        _check(load().tvs_job_result(self.ctx._h, self._h, _dev(d_out, (n2, n1), self.dtype),
+                                     _dev(tau_out, (2, n2 + 1, n1 + 1), self.dtype), st,
+                                     _stream(dev)))
+        return d_out, tau_out, [st[0].as_dict(), st[1].as_dict()]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().tvs_job_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,29 @@
+"""Host-side job footprints (no GPU needed): they grow with the image, double
+from float32 to float64 for the resident state, and include the overlap
+frames and plans a layout adds."""
+import pytest
+
+torch = pytest.importorskip("torch")
+
+
+def fp(shape, dtype, lay, its=(2, 3)):
+    from paper_2602_17494_amd import job_footprint, make_iters, make_layout
+    return job_footprint(shape, dtype, make_layout(*lay), make_iters(*its))
+
+
+def test_footprint_properties():
+    try:
+        from paper_2602_17494_amd import load
+        load()
+    except Exception as e:  # library not built here
+        pytest.skip(str(e))
+    a = fp((64, 64), torch.float32, (1, 1, 0, 0))
+    b = fp((128, 128), torch.float32, (1, 1, 0, 0))
+    assert 0 < a < b
+    c = fp((128, 128), torch.float64, (1, 1, 0, 0))
+    table = 8 * 130 * 130
+    assert 1.9 * (b - table) < c - table < 2.1 * (b - table)
+    d = fp((128, 128), torch.float32, (2, 2, 8, 8))
+    assert d > b  # local frames and plans on top of the global ones
+    with pytest.raises(Exception):
+        fp((1, 8), torch.float32, (1, 1, 0, 0))
