@@ -46,7 +46,141 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (counter calibration)")
+    ap.add_argument("--batch", action="store_true",
+                    help="instead: a batch of 64 images of uneven sizes as resident jobs, one "
+                         "batch call per Schwarz sweep, against solving them one by one")
+    ap.add_argument("--serve", action="store_true",
+                    help="instead: Poisson arrivals through the continuous-batching server, "
+                         "against plain single-domain FP64 solves served one at a time")
+    ap.add_argument("--requests", type=int, default=24, help="requests in --serve mode")
     return ap.parse_args()
+
+
+def batch_mode(args):
+    """64 images, sides uniform in {128, 256, 512, 1024}, float32; layout 4x4
+    with s = 8 up to 256, 8x8 from 512 (s = 16 at 1024); every image a job,
+    all advanced by one sweep per batch call until all are done.  Compared with
+    the same images solved one after another (tvs_schwarz_solve)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2602_17494_amd import Context, make_iters, make_layout, make_params
+    ctx = Context(0)
+    rng = np.random.default_rng(4)
+    its = make_iters(args.sweeps, args.inner)
+    work = []
+    for k in range(64):
+        n = int(rng.choice([128, 256, 512, 1024]))
+        lay = (4, 4, 8, 8) if n <= 256 else (8, 8, 16 if n == 1024 else 8, 16 if n == 1024 else 8)
+        _, d64 = synth.noisy_f32(n, n, args.sigma, 4000 + k)
+        delta, alpha = synth.params_for_sigma(args.sigma)
+        work.append((torch.tensor(d64, dtype=torch.float32, device="cuda:0"),
+                     make_params(delta, alpha), make_layout(*lay)))
+    pix = sum(((d.shape[0] + 1) ** 2 + d.shape[0] ** 2) for d, _, _ in work) * args.sweeps * args.inner
+    # one by one (plans cached in the context after a first pass)
+    for d0, prm, lay in work:
+        ctx.schwarz_solve(d0, prm, lay, make_iters(1, 1), stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d0, prm, lay in work:
+        ctx.schwarz_solve(d0, prm, lay, its, stats=False)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    # as jobs: creation (plans, copies) outside the timed region
+    jobs = [ctx.job(d0, prm, lay, its) for d0, prm, lay in work]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    calls = 0
+    while True:
+        live = [j for j in jobs if not j.done]
+        if not live:
+            break
+        ctx.batch_sweep(live)
+        calls += 1
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    out = {"metric": "Mpix*iter/s, batch of 64 uneven images (FP32 Schwarz, both steps)",
+           "value": round(pix / t_batch / 1e6, 1), "unit": "Mpix*iter/s",
+           "seconds": round(t_batch, 3), "batch_calls": calls,
+           "one_by_one": {"seconds": round(t_seq, 3), "mpix_iter_s": round(pix / t_seq / 1e6, 1)},
+           "megapixels": round(sum(d.numel() for d, _, _ in work) / 1e6, 2),
+           "sweeps": args.sweeps, "inner": args.inner, "dtype": "f32", "data": "synthetic"}
+    for j in jobs:
+        j.close()
+    print(json.dumps(out), flush=True)
+
+
+def serve_mode(args):
+    """Poisson arrivals, sides uniform in [256, 2048], sigma uniform in
+    [0.05, 0.2], float32 with FP64 reductions, layout M = clamp(round(N/256),
+    1, 8) per axis with s = 16, 10 sweeps x 100 inner per step, admission by
+    footprint within 64 GB.  The same requests are then served one at a time
+    as plain single-domain FP64 solves with 1000 dual iterations per step.
+    The arrival rate is 0.7 of the measured plain-FP64 capacity."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2602_17494_amd import Context, make_iters, make_layout, make_params
+    from paper_2602_17494_amd.serve import Request, latency_summary, serve
+    ctx = Context(0)
+    rng = np.random.default_rng(5)
+    its = make_iters(10, 100)
+    its_plain = make_iters(1, 1000)
+    specs = []
+    for k in range(args.requests):
+        n = int(rng.integers(256, 2049))
+        sigma = float(rng.uniform(0.05, 0.2))
+        m = max(1, min(8, round(n / 256)))
+        specs.append((k, n, sigma, m))
+    imgs = {}
+    for k, n, sigma, m in specs:
+        _, d64 = synth.noisy_f32(n, n, sigma, 5000 + k)
+        imgs[k] = d64
+    # plain FP64 capacity: time each request's plain solve (warm plans first)
+    plain_t = {}
+    for k, n, sigma, m in specs:
+        delta, alpha = synth.params_for_sigma(sigma)
+        d0 = torch.tensor(imgs[k], dtype=torch.float64, device="cuda:0")
+        ctx.schwarz_solve(d0, make_params(delta, alpha), make_layout(), make_iters(1, 1), stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.schwarz_solve(d0, make_params(delta, alpha), make_layout(), its_plain, stats=False)
+        torch.cuda.synchronize()
+        plain_t[k] = time.perf_counter() - t0
+    mean_service = float(np.mean(list(plain_t.values())))
+    rate = 0.7 / mean_service
+    arrivals, t = [], 0.0
+    for _ in specs:
+        t += float(rng.exponential(1.0 / rate))
+        arrivals.append(t)
+    # the plain FP64 server: FIFO, one request at a time (service times measured above)
+    free, lat_plain = 0.0, []
+    for (k, *_), a in zip(specs, arrivals):
+        start = max(free, a)
+        free = start + plain_t[k]
+        lat_plain.append(free - a)
+    reqs = []
+    for (k, n, sigma, m), a in zip(specs, arrivals):
+        delta, alpha = synth.params_for_sigma(sigma)
+        d0 = torch.tensor(imgs[k], dtype=torch.float32, device="cuda:0")
+        lay = make_layout(m, m, 16 if m > 1 else 0, 16 if m > 1 else 0)
+        reqs.append(Request(k, d0, make_params(delta, alpha), lay, its, arrival=a))
+    t0 = time.perf_counter()
+    results, srv = serve(ctx, reqs, 64 << 30)
+    wall = time.perf_counter() - t0
+    pix = sum(((n + 1) ** 2 + n * n) for _, n, _, _ in specs) * 10 * 100
+    lat = latency_summary(results)
+    out = {"metric": "continuous-batching serving, FP32 Schwarz jobs (10 sweeps x 100 inner per step)",
+           "requests": len(results), "rate_per_s": round(rate, 3),
+           "throughput_mpix_iter_s": round(pix / wall / 1e6, 1),
+           "latency_s": {"p50": round(lat["p50"], 4), "p99": round(lat["p99"], 4)},
+           "rounds": srv.rounds, "peak_bytes": srv.peak_in_use,
+           "plain_fp64_fifo": {"latency_s": {"p50": round(float(np.percentile(lat_plain, 50)), 4),
+                                              "p99": round(float(np.percentile(lat_plain, 99)), 4)},
+                               "mean_service_s": round(mean_service, 4),
+                               "dual_iterations_per_step": 1000},
+           "data": "synthetic"}
+    print(json.dumps(out), flush=True)
 
 
 def calibrate_copy():
@@ -131,6 +265,13 @@ def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.batch or args.serve:
+        import torch
+        if not torch.cuda.is_available():
+            print("no GPU available", file=sys.stderr)
+            sys.exit(1)
+        batch_mode(args) if args.batch else serve_mode(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "

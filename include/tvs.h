@@ -198,12 +198,16 @@ int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* lau
  *                      caller may reuse it on return) and run the Step-1
  *                      set-up on `stream`; the call waits for that work
  *   tvs_batch_sweep    advance each of the n jobs (of this context) by one
- *                      sweep of its current step, in order, on `stream`; the
- *                      sweep that completes Step 1 also computes tau and its
- *                      statistics (which waits for the stream) and sets up
- *                      Step 2; the one that completes Step 2 computes d.  A
- *                      finished job is left as it is.  Jobs sharing nothing,
- *                      the order of the list does not change any result.
+ *                      sweep of its current step, ordered after the work
+ *                      already on `stream`, and make `stream` wait for it;
+ *                      with several jobs the context spreads them over up to
+ *                      4 streams of its own, so that their kernels overlap
+ *                      on the device.  The sweep that completes Step 1 also
+ *                      computes tau and its statistics (which waits for that
+ *                      job's work) and sets up Step 2; the one that completes
+ *                      Step 2 computes d.  A finished job is left as it is.
+ *                      Jobs share no data: neither the order of the list nor
+ *                      the overlap changes any result.
  *   tvs_job_status     step 1 or 2 (3 when finished), sweeps done in it,
  *                      done = 1 when finished; any pointer may be NULL
  *   tvs_job_result     copy d (N2 x N1) and tau (2 x (N2+1) x (N1+1)) into

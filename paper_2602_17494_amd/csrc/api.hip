@@ -231,6 +231,18 @@ struct tvs_ctx {
   tvs::DevBuf partials;  // FP64 partial sums
   tvs::DevBuf scal;      // FP64 results (energies per sweep, gap)
   size_t scal_cap = 0;
+  // streams a batch call spreads independent jobs over (default priority),
+  // with the events that fork them from and join them to the caller's stream
+  static constexpr int kBatchStreams = 4;
+  hipStream_t bstream[kBatchStreams] = {};
+  hipEvent_t bfork = nullptr, bjoin[kBatchStreams] = {};
+  ~tvs_ctx() {
+    for (int k = 0; k < kBatchStreams; ++k) {
+      if (bstream[k]) (void)hipStreamDestroy(bstream[k]);
+      if (bjoin[k]) (void)hipEventDestroy(bjoin[k]);
+    }
+    if (bfork) (void)hipEventDestroy(bfork);
+  }
 };
 
 namespace tvs {
@@ -1072,12 +1084,34 @@ int tvs_batch_sweep(tvs_ctx* ctx, tvs_job* const* jobs, int n, void* stream) {
       if (!jobs[i] || jobs[i]->ctx != ctx) throw Error(TVS_EINVAL, "job missing or of another context");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < n; ++i) {
-      tvs_job* j = jobs[i];
+    auto sweep_on = [&](tvs_job* j, hipStream_t st) {
       if (j->dtype == TVS_F32)
-        job_sweep<float>(ctx, j, s);
+        job_sweep<float>(ctx, j, st);
       else
-        job_sweep<double>(ctx, j, s);
+        job_sweep<double>(ctx, j, st);
+    };
+    if (n < 2) {
+      if (n == 1) sweep_on(jobs[0], s);
+      return;
+    }
+    // The jobs share no device data, so their sweeps may run concurrently:
+    // fork from the caller's stream onto the context's batch streams, deal
+    // the jobs round-robin, and join back (every job's launches stay on one
+    // stream and keep their order, so no result changes).
+    const int K = std::min(n, tvs_ctx::kBatchStreams);
+    if (!ctx->bfork) {
+      TVS_HIP(hipEventCreateWithFlags(&ctx->bfork, hipEventDisableTiming));
+      for (int k = 0; k < tvs_ctx::kBatchStreams; ++k) {
+        TVS_HIP(hipStreamCreateWithFlags(&ctx->bstream[k], hipStreamNonBlocking));
+        TVS_HIP(hipEventCreateWithFlags(&ctx->bjoin[k], hipEventDisableTiming));
+      }
+    }
+    TVS_HIP(hipEventRecord(ctx->bfork, s));
+    for (int k = 0; k < K; ++k) TVS_HIP(hipStreamWaitEvent(ctx->bstream[k], ctx->bfork, 0));
+    for (int i = 0; i < n; ++i) sweep_on(jobs[i], ctx->bstream[i % K]);
+    for (int k = 0; k < K; ++k) {
+      TVS_HIP(hipEventRecord(ctx->bjoin[k], ctx->bstream[k]));
+      TVS_HIP(hipStreamWaitEvent(s, ctx->bjoin[k], 0));
     }
   });
 }
