@@ -202,7 +202,11 @@ int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* lau
  *                      already on `stream`, and make `stream` wait for it;
  *                      with several jobs the context spreads them over up to
  *                      4 streams of its own, so that their kernels overlap
- *                      on the device.  The sweep that completes Step 1 also
+ *                      on the device.  The part of a sweep that is the same
+ *                      in every sweep (the subdomain prologue, the inner
+ *                      iterations and the combination) is recorded as a HIP
+ *                      graph the first time and replayed afterwards, unless
+ *                      kernel timing is on.  The sweep that completes Step 1 also
  *                      computes tau and its statistics (which waits for that
  *                      job's work) and sets up Step 2; the one that completes
  *                      Step 2 computes d.  A finished job is left as it is.

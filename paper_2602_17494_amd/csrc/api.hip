@@ -465,18 +465,21 @@ struct Step1Run {
   // One sweep; false once the run has no sweep left (count reached, or the
   // stopping residual fell below the tolerance, which reads it back).
   bool sweep(hipStream_t s) {
+    if (!head(s)) return false;
+    body(s, true);
+    return !finished;
+  }
+
+  // a2 and the stopping test: the part of a sweep that depends on its index
+  // (the FP64 energy lands in e[n]); false when the run stops here.
+  bool head(hipStream_t s) {
     if (finished) return false;
     const Grid g = P->g;
-    const SubFrames& sf = P->ss.sf;
     const T inv_h = cs.inv_h;
-    const Frame gf = global_frame(g);
-    const Frame f2p = sub_frame(sf, 2), f1p = sub_frame(sf, 1);
-    const long long gpl = (long long)g.n2 * g.n1;
-    const double px = P->ss.sub_px, esz = sizeof(T);
-    const char* ltag = P->plain ? "s1_plain" : "s1_local";
     // a2: r^n = f - P_K vecdiv p^n (global, once per sweep) and D(p^n)
     launch_global_vecdiv<T>(dptr<T>(P->p), g, inv_h, dptr<T>(P->zg), s);
-    P->global->apply_div(dptr<T>(P->zg), gf, dptr<T>(P->phig), Frame{0, 0, g.n1}, s, tm, "s1_global");
+    P->global->apply_div(dptr<T>(P->zg), global_frame(g), dptr<T>(P->phig), Frame{0, 0, g.n1}, s, tm,
+                         "s1_global");
     launch_residual<T>(dptr<T>(P->f1), dptr<T>(P->zg), dptr<T>(P->phig), g, inv_h, dptr<T>(P->r), part, e + n, s);
     if (its.tol > 0 && n >= 1) {
       double hv[2];
@@ -487,9 +490,24 @@ struct Step1Run {
         return false;
       }
     }
+    return true;
+  }
+
+  // the rest of the sweep (a2's omega prologue, a3, a4): the same launches
+  // in every sweep, up to the exchange of the ping-pong buffers, so that a
+  // caller may record them once in a graph and replay it; with launch =
+  // false only the host-side state advances (the graph did the work).
+  void body(hipStream_t s, bool launch) {
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
+    const T inv_h = cs.inv_h;
+    const Frame f2p = sub_frame(sf, 2), f1p = sub_frame(sf, 1);
+    const long long gpl = (long long)g.n2 * g.n1;
+    const double px = P->ss.sub_px, esz = sizeof(T);
+    const char* ltag = P->plain ? "s1_plain" : "s1_local";
     const T* omega = dptr<T>(P->omega);
     GreenPlan<T>& plan = lp();
-    if (!P->plain) {
+    if (launch && !P->plain) {
       // omega_m = R_{m,+} r^n + LP_m(vecdiv(theta_m p^n))
       launch_sub_theta_p<T>(sf, g, dptr<T>(P->p), 4, dptr<T>(P->vt), s);
       launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P->vt), dptr<T>(P->zw), s);
@@ -499,23 +517,27 @@ struct Step1Run {
     // a3: inner iterations, warm-started from the previous sweep's q_m:
     // phi = Delta^+ div z on the Green box, the update of v, z' = vecdiv v'
     for (int nu = 0; nu < its.inner; ++nu) {
-      plan.apply_div(zcur, f2p, dptr<T>(P->phi), f1p, s, tm, ltag);
-      KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
-        launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P->phi), omega, nxt, s);
-      });
-      KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
-                        [&] { launch_sub_vecdiv<T>(sf, g, inv_h, nxt, znxt, s); });
+      if (launch) {
+        plan.apply_div(zcur, f2p, dptr<T>(P->phi), f1p, s, tm, ltag);
+        KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
+          launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P->phi), omega, nxt, s);
+        });
+        KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
+                          [&] { launch_sub_vecdiv<T>(sf, g, inv_h, nxt, znxt, s); });
+      }
       std::swap(cur, nxt);
       std::swap(zcur, znxt);
     }
     // a4: p^{n+1} = (1 - ahat) p^n + ahat sum_m q_m
-    KernelTimer::time(tm, "s1_combine", 4 * esz * (2.0 * gpl + px), s,
-                      [&] { launch_combine<T>(sf, g, 4, cs.ahat, cur, dptr<T>(P->p), s); });
+    if (launch)
+      KernelTimer::time(tm, "s1_combine", 4 * esz * (2.0 * gpl + px), s,
+                        [&] { launch_combine<T>(sf, g, 4, cs.ahat, cur, dptr<T>(P->p), s); });
     ++done;
     ++n;
     if (n >= its.sweeps) finished = true;
-    return !finished;
   }
+  // which of the two ping-pong states the next body starts from
+  int parity() const { return cur == dptr<T>(P->va) ? 0 : 1; }
 
   void end(T* tau_out, tvs_stats* st, hipStream_t s) {
     const Grid g = P->g;
@@ -608,12 +630,15 @@ struct Step2Run {
   }
 
   bool sweep(hipStream_t s) {
+    if (!head(s)) return false;
+    body(s, true);
+    return !finished;
+  }
+
+  // the energy of p^n (into e[n]) and the stopping test
+  bool head(hipStream_t s) {
     if (finished) return false;
-    const Grid g = P->g;
-    const SubFrames& sf = P->ss.sf;
-    const long long gpl = (long long)N2 * N1;
-    const double px = P->ss.sub_px, esz = sizeof(T);
-    launch_energy_rof<T>(dptr<T>(P->p), dptr<T>(P->f2), g, cs.inv_h, part, e + n, s);
+    launch_energy_rof<T>(dptr<T>(P->p), dptr<T>(P->f2), P->g, cs.inv_h, part, e + n, s);
     if (its.tol > 0 && n >= 1) {
       double hv[2];
       TVS_HIP(hipMemcpyAsync(hv, e + n - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -623,22 +648,33 @@ struct Step2Run {
         return false;
       }
     }
+    return true;
+  }
+
+  // a7-a9, the same launches in every sweep (see Step1Run::body)
+  void body(hipStream_t s, bool launch) {
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
+    const long long gpl = (long long)N2 * N1;
+    const double px = P->ss.sub_px, esz = sizeof(T);
     // a7: b_m = div((1 - theta_m) p^n) - f near the subdomain
-    launch_sub2_prologue<T>(sf, g, cs.inv_h, dptr<T>(P->p), dptr<T>(P->f2), dptr<T>(P->b), s);
+    if (launch) launch_sub2_prologue<T>(sf, g, cs.inv_h, dptr<T>(P->p), dptr<T>(P->f2), dptr<T>(P->b), s);
     // a8: inner iterations
     for (int nu = 0; nu < its.inner; ++nu) {
-      KernelTimer::time(tm, "s2_update", 5 * esz * px, s,
-                        [&] { launch_sub2_update<T>(sf, g, cs, cur, dptr<T>(P->b), nxt, s); });
+      if (launch)
+        KernelTimer::time(tm, "s2_update", 5 * esz * px, s,
+                          [&] { launch_sub2_update<T>(sf, g, cs, cur, dptr<T>(P->b), nxt, s); });
       std::swap(cur, nxt);
     }
     // a9: combine
-    KernelTimer::time(tm, "s2_combine", 2 * esz * (2.0 * gpl + px), s,
-                      [&] { launch_combine<T>(sf, g, 2, cs.ahat, cur, dptr<T>(P->p), s); });
+    if (launch)
+      KernelTimer::time(tm, "s2_combine", 2 * esz * (2.0 * gpl + px), s,
+                        [&] { launch_combine<T>(sf, g, 2, cs.ahat, cur, dptr<T>(P->p), s); });
     ++done;
     ++n;
     if (n >= its.sweeps) finished = true;
-    return !finished;
   }
+  int parity() const { return cur == dptr<T>(P->va) ? 0 : 1; }
 
   void end(T* d_out, tvs_stats* st, hipStream_t s) {
     const Grid g = P->g;
@@ -734,6 +770,17 @@ struct JobState {
   std::unique_ptr<Step2Problem<T>> p2;
   std::unique_ptr<Step1Run<T>> r1;
   std::unique_ptr<Step2Run<T>> r2;
+  // the sweep bodies of both steps recorded as graphs, per ping-pong parity
+  hipGraphExec_t g1[2] = {}, g2[2] = {};
+  JobState() = default;
+  JobState(const JobState&) = delete;
+  JobState& operator=(const JobState&) = delete;
+  ~JobState() {
+    for (int k = 0; k < 2; ++k) {
+      if (g1[k]) (void)hipGraphExecDestroy(g1[k]);
+      if (g2[k]) (void)hipGraphExecDestroy(g2[k]);
+    }
+  }
   size_t bytes() const {
     return d0.bytes + tau.bytes + dout.bytes + part.bytes + e1.bytes + e2.bytes + p1->bytes() +
            p2->bytes();
@@ -820,13 +867,50 @@ void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s) {
     j->d = std::move(st);
 }
 
+// One sweep of a run: its head eagerly, its body from a graph recorded the
+// first time the body starts from this ping-pong parity (the recording is
+// then launched once to do the work).  Without graphs (kernel timing on, so
+// that every launch keeps its own events) the body runs eagerly.
+template <typename Run>
+bool graph_sweep(Run& run, hipGraphExec_t (&gx)[2], bool graphs, hipStream_t s) {
+  if (!run.head(s)) return false;
+  if (!graphs) {
+    run.body(s, true);
+    return !run.finished;
+  }
+  const int par = run.parity();
+  if (gx[par]) {
+    TVS_HIP(hipGraphLaunch(gx[par], s));
+    run.body(s, false);
+    return !run.finished;
+  }
+  hipGraph_t g = nullptr;
+  TVS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  try {
+    run.body(s, true);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  TVS_HIP(hipStreamEndCapture(s, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw Error(TVS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  gx[par] = ex;
+  TVS_HIP(hipGraphLaunch(ex, s));
+  return !run.finished;
+}
+
 // one sweep of the job's current step; the step's end (and the next step's
 // begin) follow the sweep that completes it
 template <typename T>
 void job_sweep(tvs_ctx* c, tvs_job* j, hipStream_t s) {
   JobState<T>& st = job_state<T>(j);
+  const bool graphs = !c->timer.on;
   if (j->step == 1) {
-    if (!st.r1->sweep(s)) {
+    if (!graph_sweep(*st.r1, st.g1, graphs, s)) {
       st.r1->end(st.tau.template as<T>(), &j->st[0], s);
       st.r2 = std::make_unique<Step2Run<T>>(*st.p2, st.d0.template as<T>(), j->N2, j->N1, &j->prm, &j->lay,
                                             &j->its, Partials{st.part.template as<double>(), 1024},
@@ -835,7 +919,7 @@ void job_sweep(tvs_ctx* c, tvs_job* j, hipStream_t s) {
       j->step = 2;
     }
   } else if (j->step == 2) {
-    if (!st.r2->sweep(s)) {
+    if (!graph_sweep(*st.r2, st.g2, graphs, s)) {
       st.r2->end(st.dout.template as<T>(), &j->st[1], s);
       j->step = 3;
     }
@@ -1090,14 +1174,13 @@ int tvs_batch_sweep(tvs_ctx* ctx, tvs_job* const* jobs, int n, void* stream) {
       else
         job_sweep<double>(ctx, j, st);
     };
-    if (n < 2) {
-      if (n == 1) sweep_on(jobs[0], s);
-      return;
-    }
+    if (n == 0) return;
     // The jobs share no device data, so their sweeps may run concurrently:
     // fork from the caller's stream onto the context's batch streams, deal
     // the jobs round-robin, and join back (every job's launches stay on one
-    // stream and keep their order, so no result changes).
+    // stream and keep their order, so no result changes).  The batch streams
+    // are also where sweep bodies are recorded as graphs (the caller's
+    // stream may be the legacy default stream, which cannot be captured).
     const int K = std::min(n, tvs_ctx::kBatchStreams);
     if (!ctx->bfork) {
       TVS_HIP(hipEventCreateWithFlags(&ctx->bfork, hipEventDisableTiming));

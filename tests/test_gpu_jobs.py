@@ -149,3 +149,34 @@ def test_serving_loop_interleaves_and_matches_alone(ctx):
         assert r.finished >= r.admitted >= 0
     lat = latency_summary(results)
     assert lat["n"] == 10 and lat["p99"] >= lat["p50"] > 0
+
+
+def test_graph_replays_match_eager_sweeps(ctx):
+    """Sweep bodies are replayed from recorded graphs (kernel timing off) or
+    run eagerly (timing on).  Two jobs on the same image, advanced one sweep
+    at a time with synchronisations and eager work of their own between the
+    replays (five sweeps with an even inner count replay one graph four
+    times per step): both equal the one-shot solve bit for bit."""
+    from paper_2602_17494_amd import make_iters, make_layout, make_params
+    _, d64 = synth.noisy_f32(52, 44, 0.1, 21)
+    d0 = torch.tensor(d64, dtype=torch.float32, device=DEV)
+    prm, L, its = make_params(0.15, 10.0), make_layout(2, 2, 4, 4), make_iters(5, 4)
+    d_ref, tau_ref, _ = one_shot(ctx, d0, prm, L, its)
+    graph_job = ctx.job(d0, prm, L, its)
+    ctx.timing(True)
+    eager_job = ctx.job(d0, prm, L, its)
+    ctx.timing(False)
+    while not graph_job.done:
+        ctx.batch_sweep([graph_job])
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.batch_sweep([eager_job])
+        ctx.timing(False)
+        torch.cuda.synchronize()
+        assert graph_job.status()[:2] == eager_job.status()[:2]
+    ctx.timing_reset()
+    for job in (graph_job, eager_job):
+        d, tau, _ = job.result()
+        torch.cuda.synchronize()
+        assert torch.equal(d, d_ref) and torch.equal(tau, tau_ref)
+        job.close()
