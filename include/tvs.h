@@ -236,6 +236,36 @@ int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_s
 size_t tvs_job_bytes(const tvs_job* job);
 int tvs_job_destroy(tvs_job* job);
 
+/* Checkpoint and resume: a job's state between two sweeps (Algorithm 2's
+ * outer iterate p^n of the current step, the subdomain duals q_m^n that the
+ * next sweep's inner iterations start from, the FP64 energy history, the
+ * sweep counters, and d0 and tau), copied into one host-memory blob that a
+ * job created from it, in this or another context or process, continues from
+ * as the original would have: the restored job's results equal the
+ * uninterrupted job's bit for bit.  The blob is a versioned header followed
+ * by the raw arrays in the job's dtype; it is portable between processes on
+ * the same library version, not between versions.  The header begins with
+ * char magic[8] = "TVSJOBST", uint32 version, uint32 header bytes, uint64
+ * blob bytes, then int32 dtype, N2, N1 (native byte order).
+ *   tvs_job_export_state  with buf == NULL: *bytes = the blob size (about
+ *                      4 (Step 1) or 2 (Step 2) image planes on the grid plus
+ *                      the subdomain frames, in the job's dtype; no device
+ *                      work); otherwise copy the blob into the host buffer
+ *                      buf of cap bytes (TVS_EINVAL if cap is too small),
+ *                      ordered after the work already on `stream` (the
+ *                      stream the job's sweeps were joined to), and wait for
+ *                      the copy; the job itself is unchanged
+ *   tvs_job_import_state  validate the blob (magic, version, sizes, and the
+ *                      parameters as tvs_job_create does; TVS_EINVAL
+ *                      otherwise), build a job of its shape in ctx, recompute
+ *                      what is derived from d0 and tau on `stream` and load
+ *                      the arrays; the call waits, so the caller may free
+ *                      the blob on return.  The new job belongs to ctx and is
+ *                      freed by tvs_job_destroy. */
+int tvs_job_export_state(tvs_ctx* ctx, tvs_job* job, void* buf, size_t cap, size_t* bytes,
+                         void* stream);
+int tvs_job_import_state(tvs_ctx* ctx, const void* buf, size_t bytes, void* stream, tvs_job** out);
+
 #ifdef __cplusplus
 }
 #endif

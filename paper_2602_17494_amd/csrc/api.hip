@@ -2,6 +2,9 @@
 // Algorithm 2 for both TV-Stokes steps.
 #include <chrono>
 #include <cstdio>
+#include <cstring>
+#include <cstdint>
+#include <vector>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -843,7 +846,8 @@ template <>
 JobState<double>& job_state<double>(tvs_job* j) { return *j->d; }
 
 template <typename T>
-void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s) {
+void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s,
+                hipMemcpyKind kind = hipMemcpyDeviceToDevice) {
   auto st = std::make_unique<JobState<T>>();
   const int N2 = j->N2, N1 = j->N1;
   const size_t esz = sizeof(T);
@@ -855,7 +859,7 @@ void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s) {
   st->e2.alloc(sizeof(double) * (size_t(j->its.sweeps) + 3));
   st->p1 = make_step1<T>(c, N2, N1, j->prm.h, &j->lay, s);
   st->p2 = make_step2<T>(N2, N1, j->prm.h, &j->lay, s);
-  TVS_HIP(hipMemcpyAsync(st->d0.p, d0, esz * size_t(N2) * N1, hipMemcpyDeviceToDevice, s));
+  TVS_HIP(hipMemcpyAsync(st->d0.p, d0, esz * size_t(N2) * N1, kind, s));
   st->r1 = std::make_unique<Step1Run<T>>(*st->p1, st->d0.template as<T>(), N2, N1, &j->prm, &j->lay, &j->its,
                                          Partials{st->part.template as<double>(), 1024}, st->e1.template as<double>(), &c->timer);
   st->r1->begin(s);
@@ -903,6 +907,13 @@ bool graph_sweep(Run& run, hipGraphExec_t (&gx)[2], bool graphs, hipStream_t s) 
   return !run.finished;
 }
 
+template <typename T>
+void make_run2(tvs_ctx* c, tvs_job* j, JobState<T>& st) {
+  st.r2 = std::make_unique<Step2Run<T>>(*st.p2, st.d0.template as<T>(), j->N2, j->N1, &j->prm, &j->lay, &j->its,
+                                        Partials{st.part.template as<double>(), 1024},
+                                        st.e2.template as<double>(), &c->timer);
+}
+
 // one sweep of the job's current step; the step's end (and the next step's
 // begin) follow the sweep that completes it
 template <typename T>
@@ -912,9 +923,7 @@ void job_sweep(tvs_ctx* c, tvs_job* j, hipStream_t s) {
   if (j->step == 1) {
     if (!graph_sweep(*st.r1, st.g1, graphs, s)) {
       st.r1->end(st.tau.template as<T>(), &j->st[0], s);
-      st.r2 = std::make_unique<Step2Run<T>>(*st.p2, st.d0.template as<T>(), j->N2, j->N1, &j->prm, &j->lay,
-                                            &j->its, Partials{st.part.template as<double>(), 1024},
-                                            st.e2.template as<double>(), &c->timer);
+      make_run2(c, j, st);
       st.r2->begin(st.tau.template as<T>(), s);
       j->step = 2;
     }
@@ -924,6 +933,166 @@ void job_sweep(tvs_ctx* c, tvs_job* j, hipStream_t s) {
       j->step = 3;
     }
   }
+}
+
+// ---- a job's state between sweeps, as one host blob (checkpoint/resume) ----
+// Between two sweeps a run is described by its dual variables (the global p
+// and the resident subdomain duals of the ping-pong state the next sweep
+// starts from, with their vecdiv in Step 1), its FP64 energy history and its
+// counters; everything else (tau_0, f, omega, the Step-2 data, the plans) is
+// recomputed from d0 and tau by the same kernels, so a restored job continues
+// bit for bit as the original would have.
+constexpr char kStateMagic[8] = {'T', 'V', 'S', 'J', 'O', 'B', 'S', 'T'};
+constexpr uint32_t kStateVersion = 1;
+constexpr int kMaxSections = 6;
+
+struct StateHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  uint64_t total_bytes;
+  int32_t dtype, N2, N1, step, n, done, finished, parity;
+  tvs_params prm;
+  tvs_layout lay;
+  tvs_iters its;
+  tvs_stats st[2];
+  int32_t nsec, reserved;
+  uint64_t sec_bytes[kMaxSections];
+};
+
+struct Section {
+  void* p;
+  size_t bytes;
+};
+
+// the device arrays holding a job's state at its current step, in blob order
+template <typename T>
+std::vector<Section> state_sections(tvs_job* j) {
+  JobState<T>& st = job_state<T>(j);
+  std::vector<Section> v{{st.d0.p, st.d0.bytes}};
+  if (j->step == 1) {
+    Step1Run<T>& r = *st.r1;
+    v.push_back({r.P->p.p, r.P->p.bytes});
+    v.push_back({r.cur, r.P->va.bytes});
+    v.push_back({r.zcur, r.P->za.bytes});
+    v.push_back({st.e1.p, st.e1.bytes});
+  } else if (j->step == 2) {
+    Step2Run<T>& r = *st.r2;
+    v.push_back({st.tau.p, st.tau.bytes});
+    v.push_back({r.P->p.p, r.P->p.bytes});
+    v.push_back({r.cur, r.P->va.bytes});
+    v.push_back({st.e2.p, st.e2.bytes});
+  } else {
+    v.push_back({st.tau.p, st.tau.bytes});
+    v.push_back({st.dout.p, st.dout.bytes});
+  }
+  return v;
+}
+
+template <typename T>
+StateHeader state_header(tvs_job* j, const std::vector<Section>& secs) {
+  JobState<T>& st = job_state<T>(j);
+  StateHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kStateMagic, sizeof h.magic);
+  h.version = kStateVersion;
+  h.header_bytes = sizeof(StateHeader);
+  h.dtype = j->dtype;
+  h.N2 = j->N2;
+  h.N1 = j->N1;
+  h.step = j->step;
+  if (j->step == 1) {
+    h.n = st.r1->n;
+    h.done = st.r1->done;
+    h.finished = st.r1->finished;
+    h.parity = st.r1->parity();
+  } else {
+    h.n = st.r2->n;
+    h.done = st.r2->done;
+    h.finished = st.r2->finished;
+    h.parity = st.r2->parity();
+  }
+  h.prm = j->prm;
+  h.lay = j->lay;
+  h.its = j->its;
+  h.st[0] = j->st[0];
+  h.st[1] = j->st[1];
+  h.nsec = int32_t(secs.size());
+  h.total_bytes = sizeof(StateHeader);
+  for (size_t k = 0; k < secs.size(); ++k) {
+    h.sec_bytes[k] = secs[k].bytes;
+    h.total_bytes += secs[k].bytes;
+  }
+  return h;
+}
+
+template <typename T>
+size_t job_export(tvs_job* j, unsigned char* buf, size_t cap, hipStream_t s) {
+  const std::vector<Section> secs = state_sections<T>(j);
+  const StateHeader h = state_header<T>(j, secs);
+  if (!buf) return h.total_bytes;
+  if (cap < h.total_bytes)
+    throw Error(TVS_EINVAL, "state buffer of " + std::to_string(cap) + " bytes, " +
+                                std::to_string(h.total_bytes) + " needed");
+  std::memcpy(buf, &h, sizeof h);
+  size_t off = sizeof h;
+  for (const Section& sec : secs) {
+    TVS_HIP(hipMemcpyAsync(buf + off, sec.p, sec.bytes, hipMemcpyDeviceToHost, s));
+    off += sec.bytes;
+  }
+  TVS_HIP(hipStreamSynchronize(s));
+  return h.total_bytes;
+}
+
+// restore the state of a job that job_create has just built from the blob's
+// d0 (and the blob's shape, parameters, layout and counts)
+template <typename T>
+void job_restore(tvs_ctx* c, tvs_job* j, const StateHeader& h, const unsigned char* buf, hipStream_t s) {
+  JobState<T>& st = job_state<T>(j);
+  const int sweeps = j->its.sweeps;
+  if (h.n < 0 || h.n > sweeps || h.done < 0 || h.done > sweeps || h.parity < 0 || h.parity > 1)
+    throw Error(TVS_EINVAL, "state blob: run counters out of range");
+  if (h.nsec != (h.step == 3 ? 3 : 5)) throw Error(TVS_EINVAL, "state blob: wrong number of sections");
+  j->st[0] = h.st[0];
+  j->st[1] = h.st[1];
+  if (h.step >= 2) {
+    make_run2(c, j, st);
+    if (h.step == 2) {
+      // the Step-2 data comes from tau; the blob's tau follows d0
+      if (h.sec_bytes[1] != st.tau.bytes) throw Error(TVS_EINVAL, "state blob: tau section size mismatch");
+      TVS_HIP(hipMemcpyAsync(st.tau.p, buf + sizeof h + h.sec_bytes[0], st.tau.bytes, hipMemcpyHostToDevice, s));
+      st.r2->begin(st.tau.template as<T>(), s);
+    }
+  }
+  j->step = h.step;
+  if (h.step == 1) {
+    Step1Run<T>& r = *st.r1;
+    r.n = h.n;
+    r.done = h.done;
+    r.finished = h.finished != 0;
+    if (h.parity != r.parity()) {
+      std::swap(r.cur, r.nxt);
+      std::swap(r.zcur, r.znxt);
+    }
+  } else {
+    Step2Run<T>& r = *st.r2;
+    r.n = h.n;
+    r.done = h.done;
+    r.finished = h.step == 3 || h.finished != 0;
+    if (h.step == 2 && h.parity != r.parity()) std::swap(r.cur, r.nxt);
+  }
+  const std::vector<Section> secs = state_sections<T>(j);
+  if (int(secs.size()) != h.nsec) throw Error(TVS_EINVAL, "state blob: wrong number of sections");
+  for (size_t k = 0; k < secs.size(); ++k)
+    if (secs[k].bytes != h.sec_bytes[k])
+      throw Error(TVS_EINVAL, "state blob: section " + std::to_string(k) + " has the wrong size");
+  size_t off = sizeof h;
+  for (const Section& sec : secs) {
+    TVS_HIP(hipMemcpyAsync(sec.p, buf + off, sec.bytes, hipMemcpyHostToDevice, s));
+    off += sec.bytes;
+  }
+  // the caller may free the blob on return, and later calls may come on
+  // another stream
+  TVS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
@@ -1233,6 +1402,61 @@ int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_s
       stats[0] = job->st[0];
       stats[1] = job->st[1];
     }
+  });
+}
+
+int tvs_job_export_state(tvs_ctx* ctx, tvs_job* job, void* buf, size_t cap, size_t* bytes,
+                         void* stream) {
+  return guarded([&] {
+    if (!ctx || !job || job->ctx != ctx) throw Error(TVS_EINVAL, "bad job");
+    if (!bytes) throw Error(TVS_EINVAL, "bytes is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto* b = static_cast<unsigned char*>(buf);
+    *bytes = job->dtype == TVS_F64 ? job_export<double>(job, b, cap, s) : job_export<float>(job, b, cap, s);
+  });
+}
+
+int tvs_job_import_state(tvs_ctx* ctx, const void* buf, size_t bytes, void* stream, tvs_job** out) {
+  return guarded([&] {
+    if (!ctx || !buf || !out) throw Error(TVS_EINVAL, "NULL argument");
+    *out = nullptr;
+    StateHeader h;
+    if (bytes < sizeof h) throw Error(TVS_EINVAL, "state blob shorter than its header");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, kStateMagic, sizeof h.magic) != 0) throw Error(TVS_EINVAL, "not a job state blob");
+    if (h.version != kStateVersion || h.header_bytes != sizeof h)
+      throw Error(TVS_EINVAL, "job state blob of another version");
+    if (h.total_bytes != bytes) throw Error(TVS_EINVAL, "state blob size does not match its header");
+    if (h.dtype != TVS_F32 && h.dtype != TVS_F64) throw Error(TVS_EINVAL, "state blob: unknown dtype");
+    if (h.step < 1 || h.step > 3 || h.nsec < 1 || h.nsec > kMaxSections)
+      throw Error(TVS_EINVAL, "state blob: bad step or section count");
+    uint64_t sum = sizeof h;
+    for (int k = 0; k < h.nsec; ++k) sum += h.sec_bytes[k];
+    if (sum != h.total_bytes) throw Error(TVS_EINVAL, "state blob: section sizes do not add up");
+    check_params(&h.prm, h.N2, h.N1);
+    check_iters(&h.its);
+    const size_t esz = h.dtype == TVS_F64 ? sizeof(double) : sizeof(float);
+    if (h.sec_bytes[0] != esz * size_t(h.N2) * h.N1) throw Error(TVS_EINVAL, "state blob: d0 section size mismatch");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto j = std::make_unique<tvs_job>();
+    j->ctx = ctx;
+    j->dtype = tvs_dtype(h.dtype);
+    j->N2 = h.N2;
+    j->N1 = h.N1;
+    j->prm = h.prm;
+    j->lay = h.lay;
+    j->its = h.its;
+    const auto* b = static_cast<const unsigned char*>(buf);
+    if (j->dtype == TVS_F32) {
+      job_create<float>(ctx, j.get(), reinterpret_cast<const float*>(b + sizeof h), s, hipMemcpyHostToDevice);
+      job_restore<float>(ctx, j.get(), h, b, s);
+    } else {
+      job_create<double>(ctx, j.get(), reinterpret_cast<const double*>(b + sizeof h), s, hipMemcpyHostToDevice);
+      job_restore<double>(ctx, j.get(), h, b, s);
+    }
+    *out = j.release();
   });
 }
 

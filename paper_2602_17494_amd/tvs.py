@@ -9,6 +9,8 @@ any other implementation.
 import ctypes
 import os
 
+import numpy as np
+
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -100,6 +102,10 @@ def load():
     lib.tvs_job_result.restype = ci
     lib.tvs_job_bytes.argtypes = [vp]
     lib.tvs_job_bytes.restype = sz
+    lib.tvs_job_export_state.argtypes = [vp, vp, vp, sz, ctypes.POINTER(sz), vp]
+    lib.tvs_job_export_state.restype = ci
+    lib.tvs_job_import_state.argtypes = [vp, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.tvs_job_import_state.restype = ci
     lib.tvs_job_destroy.argtypes = [vp]
     lib.tvs_job_destroy.restype = ci
     _lib = lib
@@ -110,7 +116,7 @@ EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_byte
             "tvs_step2", "tvs_schwarz_solve", "tvs_project_div_free", "tvs_timing_enable",
             "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get", "tvs_job_footprint",
             "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
-            "tvs_job_bytes", "tvs_job_destroy"]
+            "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state"]
 
 
 def _check(code):
@@ -163,6 +169,17 @@ class Context:
         _check(lib.tvs_ctx_create(int(device), ctypes.byref(h)))
         self._h = h
         self.device = torch.device("cuda", int(device))
+
+    def export_state(self):
+        """The job's state between sweeps as a host uint8 array (a checkpoint
+        that Context.import_job resumes from)."""
+        lib, dev = load(), self.ctx.device
+        n = ctypes.c_size_t()
+        _check(lib.tvs_job_export_state(self.ctx._h, self._h, None, 0, ctypes.byref(n), _stream(dev)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(lib.tvs_job_export_state(self.ctx._h, self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size,
+                                        ctypes.byref(n), _stream(dev)))
+        return buf
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -253,6 +270,17 @@ class Context:
                                      _stream(d0.device), ctypes.byref(h)))
         return Job(self, h, n2, n1, d0.dtype)
 
+    def import_job(self, state):
+        """A job resumed from a blob of Job.export_state (bytes or a uint8
+        array); its dtype and shape are the blob's."""
+        buf = np.ascontiguousarray(np.frombuffer(state, dtype=np.uint8))
+        h = ctypes.c_void_p()
+        _check(load().tvs_job_import_state(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size,
+                                           _stream(self.device), ctypes.byref(h)))
+        # header: magic[8], u32 version, u32 header bytes, u64 total, i32 dtype, N2, N1
+        code, n2, n1 = (int(x) for x in buf[24:36].view(np.int32))
+        return Job(self, h, n2, n1, torch.float64 if code == TVS_F64 else torch.float32)
+
     def batch_sweep(self, jobs):
         """Advance every job in the list by one sweep of its current step."""
         arr = (ctypes.c_void_p * max(1, len(jobs)))(*[j._h.value for j in jobs])
@@ -314,6 +342,17 @@ class Job:
                                      _dev(tau_out, (2, n2 + 1, n1 + 1), self.dtype), st,
                                      _stream(dev)))
         return d_out, tau_out, [st[0].as_dict(), st[1].as_dict()]
+
+    def export_state(self):
+        """The job's state between sweeps as a host uint8 array (a checkpoint
+        that Context.import_job resumes from)."""
+        lib, dev = load(), self.ctx.device
+        n = ctypes.c_size_t()
+        _check(lib.tvs_job_export_state(self.ctx._h, self._h, None, 0, ctypes.byref(n), _stream(dev)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(lib.tvs_job_export_state(self.ctx._h, self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size,
+                                        ctypes.byref(n), _stream(dev)))
+        return buf
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
