@@ -25,6 +25,8 @@ fusion or reordering beyond what the paper's definitions state:
   (alg:disalgsubsp), the generic inner loop Algorithm 3 (alg:tfsparinner),
   the TFS inner loop with global arrays Algorithm 4 (alg:tfsparinnertfs) and
   its localized form Algorithm 5 (alg:tfsparinnertfsloc).
+* ``quality``    -- Section 5.2: PSNR, MSSIM and the tangent-field measure
+  Perf used to pick the TFS weight.
 
 Readings of passages the paper leaves open are listed in each function's
 docstring.  Pins (independent checks) live in ``tests/test_oracle_*.py``.
