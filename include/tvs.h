@@ -236,6 +236,30 @@ int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_s
 size_t tvs_job_bytes(const tvs_job* job);
 int tvs_job_destroy(tvs_job* job);
 
+/* Quality measures of Section 5.2 (used to pick the TFS weight delta and the
+ * Step-2 parameters in the paper's experiments).
+ *   tvs_tangent_field  tau_0 = (-D^{neum-}_y d, D^{neum-}_x d) of an N2 x N1
+ *                      image d (device pointer), the tangent field of Step 1's
+ *                      data (text after eq. ir2dualdis); applied to a clean
+ *                      image it gives the ground-truth tangent field.
+ *                      tau_out: device pointer, 2 x (N2+1) x (N1+1), planes
+ *                      [tau_1, tau_2].  Stream-ordered, does not wait.
+ *   tvs_quality        of x against ref, both n2 x n1 device arrays in dtype:
+ *                      out[0] = PSNR = -10 log10 MSE (the paper fixes the
+ *                      peak value R = 1; HUGE_VAL when x == ref), out[1] =
+ *                      MSSIM (one window, the whole grid; means, variances
+ *                      and covariance normalised by n2 n1; c1 = 1e-4, c2 =
+ *                      9e-4), out[2] = MSE.  out is a host array of 3
+ *                      doubles.  The moments are FP64 sums on the device in
+ *                      two passes (means, then centred sums) in a fixed
+ *                      order; the call waits for them.  TVS_ENONFINITE if a
+ *                      moment is NaN or Inf.  Calls on one context share its
+ *                      reduction buffers: they must not overlap. */
+int tvs_tangent_field(tvs_ctx* ctx, const void* d, int N2, int N1, tvs_dtype dtype, double h, void* tau_out,
+                      void* stream);
+int tvs_quality(tvs_ctx* ctx, const void* x, const void* ref, int n2, int n1, tvs_dtype dtype, double* out,
+                void* stream);
+
 /* Checkpoint and resume: a job's state between two sweeps (Algorithm 2's
  * outer iterate p^n of the current step, the subdomain duals q_m^n that the
  * next sweep's inner iterations start from, the FP64 energy history, the

@@ -1284,6 +1284,57 @@ int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dty
   });
 }
 
+int tvs_tangent_field(tvs_ctx* ctx, const void* d, int N2, int N1, tvs_dtype dtype, double h, void* tau_out,
+                      void* stream) {
+  return guarded([&] {
+    if (!ctx || !d || !tau_out) throw Error(TVS_EINVAL, "NULL argument");
+    if (N2 < 2 || N1 < 2) throw Error(TVS_EINVAL, "image must be at least 2 x 2");
+    if ((long long)(N2 + 1) * (N1 + 1) > (1LL << 28)) throw Error(TVS_EINVAL, "image too large");
+    if (!(h > 0)) throw Error(TVS_EINVAL, "h must be > 0");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == TVS_F32)
+      launch_tau0<float>(static_cast<const float*>(d), N2, N1, float(1.0 / h), static_cast<float*>(tau_out), s);
+    else if (dtype == TVS_F64)
+      launch_tau0<double>(static_cast<const double*>(d), N2, N1, 1.0 / h, static_cast<double*>(tau_out), s);
+    else
+      throw Error(TVS_EINVAL, "unknown dtype");
+  });
+}
+
+int tvs_quality(tvs_ctx* ctx, const void* x, const void* ref, int n2, int n1, tvs_dtype dtype, double* out,
+                void* stream) {
+  return guarded([&] {
+    if (!ctx || !x || !ref || !out) throw Error(TVS_EINVAL, "NULL argument");
+    if (n2 < 1 || n1 < 1) throw Error(TVS_EINVAL, "grid must be at least 1 x 1");
+    if ((long long)n2 * n1 > (1LL << 31)) throw Error(TVS_EINVAL, "grid too large");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long n = (long long)n2 * n1;
+    double* dev = scal(ctx, 6);
+    if (dtype == TVS_F32)
+      launch_quality_moments<float>(static_cast<const float*>(x), static_cast<const float*>(ref), n, partials(ctx),
+                                    dev, s);
+    else if (dtype == TVS_F64)
+      launch_quality_moments<double>(static_cast<const double*>(x), static_cast<const double*>(ref), n,
+                                     partials(ctx), dev, s);
+    else
+      throw Error(TVS_EINVAL, "unknown dtype");
+    double m[6];
+    TVS_HIP(hipMemcpyAsync(m, dev, sizeof m, hipMemcpyDeviceToHost, s));
+    TVS_HIP(hipStreamSynchronize(s));
+    for (double v : m)
+      if (!std::isfinite(v)) throw Error(TVS_ENONFINITE, "quality: non-finite moment");
+    // Section 5.2 with R = 1: c1 = (0.01 R)^2, c2 = (0.03 R)^2
+    const double c1 = 1e-4, c2 = 9e-4, dn = double(n);
+    const double mx = m[0] / dn, mr = m[1] / dn, vx = m[2] / dn, vr = m[3] / dn, cv = m[4] / dn;
+    const double mse = m[5] / dn;
+    out[0] = mse > 0 ? -10.0 * std::log10(mse) : HUGE_VAL;
+    out[1] = (2 * mx * mr + c1) * (2 * cv + c2) / ((mx * mx + mr * mr + c1) * (vx + vr + c2));
+    out[2] = mse;
+  });
+}
+
 int tvs_job_footprint(int N2, int N1, tvs_dtype dtype, const tvs_layout* layout, const tvs_iters* iters,
                       size_t* bytes) {
   return guarded([&] {

@@ -673,6 +673,64 @@ void launch_energy_rof(const T* p, const T* f2, Grid g, T inv_h, Partials part, 
   finish_sum(part, kRedBlocks, out, s);
 }
 
+// Image-quality moments of x against r (Section 5.2): FP64 sums of x and r
+// (first pass), then of (x - mean x)^2, (r - mean r)^2, their product and
+// (x - r)^2 (second pass, centred on the first pass's means, read from the
+// device so that no host round trip separates the passes).
+constexpr int kQBlocks = 256;  // workgroups per moment; 4 moments fit 1024 partials
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments1(const T* __restrict__ x, const T* __restrict__ r, long long n,
+                                                  double* __restrict__ part) {
+  double sx = 0.0, sr = 0.0;
+  for (long long o = blockIdx.x * 256LL + threadIdx.x; o < n; o += 256LL * gridDim.x) {
+    sx += double(x[o]);
+    sr += double(r[o]);
+  }
+  sx = block_sum(sx);
+  sr = block_sum(sr);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sx;
+    part[kQBlocks + blockIdx.x] = sr;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments2(const T* __restrict__ x, const T* __restrict__ r, long long n,
+                                                  const double* __restrict__ sums, double* __restrict__ part) {
+  const double mx = sums[0] / double(n), mr = sums[1] / double(n);
+  double vx = 0.0, vr = 0.0, cv = 0.0, se = 0.0;
+  for (long long o = blockIdx.x * 256LL + threadIdx.x; o < n; o += 256LL * gridDim.x) {
+    const double a = double(x[o]), b = double(r[o]);
+    const double da = a - mx, db = b - mr, e = a - b;
+    vx += da * da;
+    vr += db * db;
+    cv += da * db;
+    se += e * e;
+  }
+  vx = block_sum(vx);
+  vr = block_sum(vr);
+  cv = block_sum(cv);
+  se = block_sum(se);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = vx;
+    part[kQBlocks + blockIdx.x] = vr;
+    part[2 * kQBlocks + blockIdx.x] = cv;
+    part[3 * kQBlocks + blockIdx.x] = se;
+  }
+}
+
+template <typename T>
+void launch_quality_moments(const T* x, const T* r, long long n, Partials part, double* out, hipStream_t s) {
+  if (part.cap < 4 * kQBlocks) throw Error(-1, "internal: partial-sum buffer too small");
+  hipLaunchKernelGGL(k_moments1<T>, dim3(kQBlocks), dim3(256), 0, s, x, r, n, part.buf);
+  TVS_LAUNCH_CHECK();
+  for (int k = 0; k < 2; ++k) finish_sum(Partials{part.buf + k * kQBlocks, kQBlocks}, kQBlocks, out + k, s);
+  hipLaunchKernelGGL(k_moments2<T>, dim3(kQBlocks), dim3(256), 0, s, x, r, n, out, part.buf);
+  TVS_LAUNCH_CHECK();
+  for (int k = 0; k < 4; ++k) finish_sum(Partials{part.buf + k * kQBlocks, kQBlocks}, kQBlocks, out + 2 + k, s);
+}
+
 // d = d0 - div p / alpha
 template <typename T>
 __global__ void k_irv2_image(const T* __restrict__ d0, const T* __restrict__ p, Grid g, T inv_h,
@@ -794,6 +852,8 @@ void launch_irv1_image(const T* d0, const T* p, const T* xi, Grid g, T inv_h, T 
   template void launch_energy_rof<T>(const T*, const T*, Grid, T, Partials, double*,            \
                                      hipStream_t);                                               \
   template void launch_irv2_image<T>(const T*, const T*, Grid, T, T, T*, hipStream_t);          \
+  template void launch_quality_moments<T>(const T*, const T*, long long, Partials, double*,      \
+                                          hipStream_t);                                          \
   template void launch_primal_rof<T>(const T*, const T*, Grid, T, T, T*, hipStream_t);          \
   template void launch_gap_rof<T>(const T*, const T*, Grid, T, Partials, double*, hipStream_t); \
   template void launch_xi<T>(const T*, int, int, T, T*, hipStream_t);                           \

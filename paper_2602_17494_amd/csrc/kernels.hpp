@@ -120,5 +120,9 @@ void launch_irv1_data(const T* d0, const T* xi, Grid g, T inv_h, T alpha, T* f2,
 template <typename T>
 void launch_irv1_image(const T* d0, const T* p, const T* xi, Grid g, T inv_h, T inv_alpha, T* d,
                        hipStream_t s);
+// FP64 moments of two n-element arrays: out[0..1] = sum x, sum r; out[2..5] =
+// sum (x - mx)^2, sum (r - mr)^2, sum (x - mx)(r - mr), sum (x - r)^2
+template <typename T>
+void launch_quality_moments(const T* x, const T* r, long long n, Partials part, double* out, hipStream_t s);
 
 }  // namespace tvs

@@ -106,6 +106,10 @@ def load():
     lib.tvs_job_export_state.restype = ci
     lib.tvs_job_import_state.argtypes = [vp, vp, sz, vp, ctypes.POINTER(vp)]
     lib.tvs_job_import_state.restype = ci
+    lib.tvs_tangent_field.argtypes = [vp, vp, ci, ci, ci, cd, vp, vp]
+    lib.tvs_tangent_field.restype = ci
+    lib.tvs_quality.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd), vp]
+    lib.tvs_quality.restype = ci
     lib.tvs_job_destroy.argtypes = [vp]
     lib.tvs_job_destroy.restype = ci
     _lib = lib
@@ -116,7 +120,8 @@ EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_byte
             "tvs_step2", "tvs_schwarz_solve", "tvs_project_div_free", "tvs_timing_enable",
             "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get", "tvs_job_footprint",
             "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
-            "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state"]
+            "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state",
+            "tvs_tangent_field", "tvs_quality"]
 
 
 def _check(code):
@@ -169,17 +174,6 @@ class Context:
         _check(lib.tvs_ctx_create(int(device), ctypes.byref(h)))
         self._h = h
         self.device = torch.device("cuda", int(device))
-
-    def export_state(self):
-        """The job's state between sweeps as a host uint8 array (a checkpoint
-        that Context.import_job resumes from)."""
-        lib, dev = load(), self.ctx.device
-        n = ctypes.c_size_t()
-        _check(lib.tvs_job_export_state(self.ctx._h, self._h, None, 0, ctypes.byref(n), _stream(dev)))
-        buf = np.empty(n.value, dtype=np.uint8)
-        _check(lib.tvs_job_export_state(self.ctx._h, self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size,
-                                        ctypes.byref(n), _stream(dev)))
-        return buf
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -285,6 +279,25 @@ class Context:
         """Advance every job in the list by one sweep of its current step."""
         arr = (ctypes.c_void_p * max(1, len(jobs)))(*[j._h.value for j in jobs])
         _check(load().tvs_batch_sweep(self._h, arr, len(jobs), _stream(self.device)))
+
+    def tangent_field(self, d, h=1.0, out=None):
+        """tau_0 = (-D_y d, D_x d) with Neumann differences, 2 x (N2+1) x (N1+1)."""
+        n2, n1 = d.shape
+        if out is None:
+            out = torch.empty((2, n2 + 1, n1 + 1), dtype=d.dtype, device=d.device)
+        _check(load().tvs_tangent_field(self._h, _dev(d, (n2, n1)), n2, n1, _dtype_code(d), float(h),
+                                        _dev(out, (2, n2 + 1, n1 + 1), d.dtype), _stream(d.device)))
+        return out
+
+    def quality(self, x, ref):
+        """{"psnr", "mssim", "mse"} of x against ref (same shape and dtype)."""
+        if x.dim() != 2:
+            raise ValueError("expected a 2-D array")
+        n2, n1 = x.shape
+        out = (ctypes.c_double * 3)()
+        _check(load().tvs_quality(self._h, _dev(x, (n2, n1)), _dev(ref, (n2, n1), x.dtype), n2, n1,
+                                  _dtype_code(x), out, _stream(x.device)))
+        return {"psnr": out[0], "mssim": out[1], "mse": out[2]}
 
     def project_div_free(self, u, h=1.0, out=None):
         _, n2, n1 = u.shape
