@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 TIMING_EVERY = 16
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32, published
 
 
 def parse():
@@ -53,6 +54,9 @@ def parse():
                     help="instead: Poisson arrivals through the continuous-batching server, "
                          "against plain single-domain FP64 solves served one at a time")
     ap.add_argument("--requests", type=int, default=24, help="requests in --serve mode")
+    ap.add_argument("--lp-compare", action="store_true",
+                    help="instead: time one Step-1 inner iteration with the image-method LP_m and "
+                         "with the block-DCT formula (float32, the bench workload's layout)")
     return ap.parse_args()
 
 
@@ -183,6 +187,59 @@ def serve_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def lp_compare_mode(args):
+    """Step 1 with 1 sweep and K inner iterations, for K = 2 and K = 12, with
+    each realisation of LP_m; the time of one inner iteration is the
+    difference over the 10 extra iterations (the set-up and the sweep's
+    global parts cancel).  For the block formula the four batched products
+    are also timed with HIP events and priced against the FP32 matrix peak."""
+    import torch
+
+    import synth
+    from paper_2602_17494_amd import TVS_LP_BLOCKDCT, TVS_LP_IMAGE, Context, make_iters, make_layout, make_params
+
+    n = args.size
+    delta, _ = synth.params_for_sigma(args.sigma)
+    _, d64 = synth.noisy_f32(n, n, args.sigma, 31)
+    dev = torch.device("cuda", 0)
+    d0 = torch.tensor(d64, dtype=torch.float32, device=dev)
+    prm, lay = make_params(delta, 1.0), make_layout(*args.layout)
+    out, taus = {}, {}
+    for name, kind in (("image", TVS_LP_IMAGE), ("blockdct", TVS_LP_BLOCKDCT)):
+        ctx = Context(0)
+        ctx.set_local_projection(kind)
+        t = {}
+        for k in (2, 12):
+            ctx.step1(d0, prm, lay, make_iters(1, k), stats=False)  # plans, warm-up
+            torch.cuda.synchronize()
+            reps = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                tau, _ = ctx.step1(d0, prm, lay, make_iters(1, k), stats=False)
+                torch.cuda.synchronize()
+                reps.append(time.perf_counter() - t0)
+            t[k] = min(reps)
+            taus[name] = tau
+        per_inner = (t[12] - t[2]) / 10
+        rec = {"ms_per_inner": per_inner * 1e3, "ctx_bytes": ctx.bytes()}
+        if kind == TVS_LP_BLOCKDCT:
+            ctx.timing(True, 1)
+            ctx.step1(d0, prm, lay, make_iters(1, 4), stats=False)
+            torch.cuda.synchronize()
+            launches, ms, flops = ctx.timing_read()["s1_bdct"]
+            ctx.timing(False)
+            tf = flops / (ms * 1e-3) / 1e12
+            rec.update({"apply_ms": ms / launches, "tflops": tf, "fp32_peak_tflops": FP32_PEAK_TFLOPS,
+                        "frac": tf / FP32_PEAK_TFLOPS})
+        out[name] = rec
+        ctx.close()
+    diff = float((taus["image"].double() - taus["blockdct"].double()).abs().max())
+    print(json.dumps({"metric": "ms per Step-1 inner iteration", "workload": f"{n}x{n} float32 Schwarz "
+                      f"{args.layout[0]}x{args.layout[1]} s={args.layout[2]}", "image": out["image"],
+                      "blockdct": out["blockdct"], "slowdown": out["blockdct"]["ms_per_inner"] /
+                      out["image"]["ms_per_inner"], "max_abs_tau_diff": diff}))
+
+
 def calibrate_copy():
     """A plain copy of known size: under rocprofv3 --pmc its FETCH_SIZE and
     WRITE_SIZE per dispatch give the factor from counter KiB to bytes."""
@@ -266,12 +323,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.batch or args.serve:
+    if args.batch or args.serve or args.lp_compare:
         import torch
         if not torch.cuda.is_available():
             print("no GPU available", file=sys.stderr)
             sys.exit(1)
-        batch_mode(args) if args.batch else serve_mode(args)
+        (batch_mode if args.batch else serve_mode if args.serve else lp_compare_mode)(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "

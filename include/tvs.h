@@ -236,6 +236,21 @@ int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_s
 size_t tvs_job_bytes(const tvs_job* job);
 int tvs_job_destroy(tvs_job* job);
 
+/* Realisation of the local projection LP_m = R P_K E of Step 1's inner
+ * iterations (eqs. locglobprojpart1, locglobprojpart3), for the later
+ * tvs_step1 and tvs_schwarz_solve calls of this context with more than one
+ * subdomain:
+ *   TVS_LP_IMAGE     (default) the inverse Laplacian of the whole grid on a
+ *                    box through the image identity and box-sized FFTs
+ *   TVS_LP_BLOCKDCT  the paper's block formula (eq. invLaplLowCapLong): the
+ *                    DCT matrix columns of the box, the spectral diagonal of
+ *                    the whole grid, four batched dense products per apply
+ *                    (about 2 n2 n1 (box side) multiply-adds per box)
+ * Both compute the same operator; results differ by rounding only.  Jobs
+ * (tvs_job_*) always use TVS_LP_IMAGE.  TVS_EINVAL for another kind. */
+enum { TVS_LP_IMAGE = 0, TVS_LP_BLOCKDCT = 1 };
+int tvs_set_local_projection(tvs_ctx* ctx, int kind);
+
 /* Quality measures of Section 5.2 (used to pick the TFS weight delta and the
  * Step-2 parameters in the paper's experiments).
  *   tvs_tangent_field  tau_0 = (-D^{neum-}_y d, D^{neum-}_x d) of an N2 x N1

@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["green.hip", "kernels.hip", "api.hip"]
+SOURCES = ["green.hip", "blockdct.hip", "kernels.hip", "api.hip"]
 LIB = os.path.join(HERE, "libtvs.so")
 
 
@@ -45,7 +45,9 @@ def build(verbose=False, jobs=3):
             sys.stderr.write(f"--- {src} ---\n{out}\n")
         raise RuntimeError("hipcc failed on " + ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(hipcc())), "lib")
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + [
+        "-L", rocm_lib, "-lrocblas", "-Wl,-rpath," + rocm_lib]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

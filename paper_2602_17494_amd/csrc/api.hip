@@ -12,6 +12,7 @@
 #include <tuple>
 
 #include "../../include/tvs.h"
+#include "blockdct.hpp"
 #include "kernels.hpp"
 
 namespace tvs {
@@ -60,7 +61,7 @@ template <> constexpr tvs_dtype dtype_of<float>() { return TVS_F32; }
 template <> constexpr tvs_dtype dtype_of<double>() { return TVS_F64; }
 
 using GridKey = std::tuple<int, int, double>;                       // n2, n1, h
-using ProbKey = std::tuple<int, int, double, int, int, int, int>;  // N2, N1, h, M2, M1, sy, sx
+using ProbKey = std::tuple<int, int, double, int, int, int, int, int>;  // N2, N1, h, M2, M1, sy, sx, LP kind
 
 struct SubSet {
   AxisLayout ay{}, ax{};
@@ -195,6 +196,7 @@ struct Step1Problem {
   SubSet ss;
   bool plain = false;
   std::unique_ptr<GreenPlan<T>> global, local;
+  std::unique_ptr<BlockDctPlan<T>> bdct;    // LP_m by the block-DCT formula instead of `local`
   DevBuf tau0, f1, r, zg, phig, p;         // global arrays on Omega-tilde
   DevBuf va, vb, vt, za, zb, zw, phi, omega;  // per-subdomain frames
   size_t bytes() const {
@@ -202,6 +204,7 @@ struct Step1Problem {
                vb.bytes + vt.bytes + za.bytes + zb.bytes + zw.bytes + phi.bytes + omega.bytes +
                global->bytes() + ss.subs_d.bytes + ss.theta_d.bytes;
     if (local) b += local->bytes();
+    if (bdct) b += bdct->bytes();
     return b;
   }
 };
@@ -231,6 +234,7 @@ struct tvs_ctx {
   std::map<tvs::GridKey, std::unique_ptr<tvs::GreenPlan<double>>> projd;
   std::map<tvs::GridKey, std::unique_ptr<tvs::DevBuf>> projtmp;
   tvs::KernelTimer timer;
+  int lp_kind = TVS_LP_IMAGE;  // realisation of LP_m for the one-shot Step-1 calls
   tvs::DevBuf partials;  // FP64 partial sums
   tvs::DevBuf scal;      // FP64 results (energies per sweep, gap)
   size_t scal_cap = 0;
@@ -312,7 +316,7 @@ double alpha_hat_of(const tvs_layout* l) {
 
 template <typename T>
 std::unique_ptr<Step1Problem<T>> make_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l,
-                                            hipStream_t s) {
+                                            hipStream_t s, int lp_kind = TVS_LP_IMAGE) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
   auto P = std::make_unique<Step1Problem<T>>();
   const int n2 = N2 + 1, n1 = N1 + 1;
@@ -326,7 +330,10 @@ std::unique_ptr<Step1Problem<T>> make_step1(tvs_ctx* c, int N2, int N1, double h
   if (!P->plain) {
     std::vector<std::array<int, 4>> boxes;
     for (auto& d : P->ss.subs) boxes.push_back({d.i0, d.j0, d.bi, d.bj});
-    P->local = std::make_unique<GreenPlan<T>>(tab, boxes, s);
+    if (lp_kind == TVS_LP_BLOCKDCT)
+      P->bdct = std::make_unique<BlockDctPlan<T>>(n2, n1, h, boxes, s);
+    else
+      P->local = std::make_unique<GreenPlan<T>>(tab, boxes, s);
   }
   const size_t gp = size_t(n2) * n1 * sizeof(T);
   P->tau0.alloc(2 * gp);
@@ -373,18 +380,18 @@ std::unique_ptr<Step2Problem<T>> make_step2(int N2, int N1, double h, const tvs_
 template <typename T>
 Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
-  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x};
+  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, c->lp_kind};
   auto& mp = s1map<T>(c);
   auto it = mp.find(key);
   if (it != mp.end()) return *it->second;
-  auto& ref = *(mp[key] = make_step1<T>(c, N2, N1, h, l, s));
+  auto& ref = *(mp[key] = make_step1<T>(c, N2, N1, h, l, s, c->lp_kind));
   return ref;
 }
 
 template <typename T>
 Step2Problem<T>& get_step2(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
-  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x};
+  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, 0};
   auto& mp = s2map<T>(c);
   auto it = mp.find(key);
   if (it != mp.end()) return *it->second;
@@ -437,7 +444,13 @@ struct Step1Run {
     const T inv_h = T(1.0 / prm.h);
     cs = StepScalars<T>{T(prm.t), inv_h, T(prm.delta), T(prm.alpha), T(alpha_hat_of(l))};
   }
-  GreenPlan<T>& lp() { return P->plain ? *P->global : *P->local; }
+  // phi = R_B Delta^dagger div u on every Green box (LP_m's inverse Laplacian)
+  void local_apply(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t s, const char* tag) {
+    if (P->bdct)
+      P->bdct->apply_div(u, uf, phi, pf, s, tm, "s1_bdct");
+    else
+      (P->plain ? *P->global : *P->local).apply_div(u, uf, phi, pf, s, tm, tag);
+  }
   double scale() const { return std::sqrt(2.0 * double(P->g.n2) * P->g.n1); }
 
   void begin(hipStream_t s) {
@@ -509,19 +522,18 @@ struct Step1Run {
     const double px = P->ss.sub_px, esz = sizeof(T);
     const char* ltag = P->plain ? "s1_plain" : "s1_local";
     const T* omega = dptr<T>(P->omega);
-    GreenPlan<T>& plan = lp();
     if (launch && !P->plain) {
       // omega_m = R_{m,+} r^n + LP_m(vecdiv(theta_m p^n))
       launch_sub_theta_p<T>(sf, g, dptr<T>(P->p), 4, dptr<T>(P->vt), s);
       launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P->vt), dptr<T>(P->zw), s);
-      plan.apply_div(dptr<T>(P->zw), f2p, dptr<T>(P->phi), f1p, s, tm, ltag);
+      local_apply(dptr<T>(P->zw), f2p, dptr<T>(P->phi), f1p, s, ltag);
       launch_sub_omega<T>(sf, g, inv_h, dptr<T>(P->r), dptr<T>(P->zw), dptr<T>(P->phi), dptr<T>(P->omega), s);
     }
     // a3: inner iterations, warm-started from the previous sweep's q_m:
     // phi = Delta^+ div z on the Green box, the update of v, z' = vecdiv v'
     for (int nu = 0; nu < its.inner; ++nu) {
       if (launch) {
-        plan.apply_div(zcur, f2p, dptr<T>(P->phi), f1p, s, tm, ltag);
+        local_apply(zcur, f2p, dptr<T>(P->phi), f1p, s, ltag);
         KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
           launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P->phi), omega, nxt, s);
         });
@@ -1281,6 +1293,14 @@ int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dty
       run_project<double>(ctx, static_cast<const double*>(u_in), n2, n1, h, static_cast<double*>(u_out), s);
     else
       throw Error(TVS_EINVAL, "unknown dtype");
+  });
+}
+
+int tvs_set_local_projection(tvs_ctx* ctx, int kind) {
+  return guarded([&] {
+    if (!ctx) throw Error(TVS_EINVAL, "NULL context");
+    if (kind != TVS_LP_IMAGE && kind != TVS_LP_BLOCKDCT) throw Error(TVS_EINVAL, "unknown local projection");
+    ctx->lp_kind = kind;
   });
 }
 

@@ -43,6 +43,22 @@ struct Frame {
   int pitch;
 };
 
+// div of a 2-plane frame field at local (r, q) of box b, with the boundary
+// rules of D^-_x, D^-_y on the whole grid and zeros outside the frame's
+// support.
+template <typename T>
+__device__ __forceinline__ T div_at(const T* __restrict__ u, const Frame& f, int b, int gi, int gj,
+                                    int r, int q, int n2, int n1, T inv_h) {
+  const T* u1 = u + b * f.box_stride;
+  const T* u2 = u1 + f.plane_stride;
+  const long long o = static_cast<long long>(r) * f.pitch + q;
+  const T a = (gj == n1 - 1) ? T(0) : u1[o];
+  const T am = (q > 0) ? u1[o - 1] : T(0);
+  const T c = (gi == n2 - 1) ? T(0) : u2[o];
+  const T cm = (r > 0) ? u2[o - f.pitch] : T(0);
+  return ((a - am) + (c - cm)) * inv_h;
+}
+
 // Tabulated torus kernel G(u, v), u in [0, n2], v in [0, n1], float64.
 struct GreenTable {
   int n2, n1;

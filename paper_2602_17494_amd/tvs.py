@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtvs.so")
 TVS_F32, TVS_F64 = 0, 1
 TVS_EBUSY = -5
 TVS_IRV2, TVS_IRV1 = 0, 1
+TVS_LP_IMAGE, TVS_LP_BLOCKDCT = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -106,6 +107,8 @@ def load():
     lib.tvs_job_export_state.restype = ci
     lib.tvs_job_import_state.argtypes = [vp, vp, sz, vp, ctypes.POINTER(vp)]
     lib.tvs_job_import_state.restype = ci
+    lib.tvs_set_local_projection.argtypes = [vp, ci]
+    lib.tvs_set_local_projection.restype = ci
     lib.tvs_tangent_field.argtypes = [vp, vp, ci, ci, ci, cd, vp, vp]
     lib.tvs_tangent_field.restype = ci
     lib.tvs_quality.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd), vp]
@@ -121,7 +124,7 @@ EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_byte
             "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get", "tvs_job_footprint",
             "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
             "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state",
-            "tvs_tangent_field", "tvs_quality"]
+            "tvs_tangent_field", "tvs_quality", "tvs_set_local_projection"]
 
 
 def _check(code):
@@ -279,6 +282,11 @@ class Context:
         """Advance every job in the list by one sweep of its current step."""
         arr = (ctypes.c_void_p * max(1, len(jobs)))(*[j._h.value for j in jobs])
         _check(load().tvs_batch_sweep(self._h, arr, len(jobs), _stream(self.device)))
+
+    def set_local_projection(self, kind):
+        """TVS_LP_IMAGE (default) or TVS_LP_BLOCKDCT for the later one-shot
+        Step-1 calls of this context."""
+        _check(load().tvs_set_local_projection(self._h, int(kind)))
 
     def tangent_field(self, d, h=1.0, out=None):
         """tau_0 = (-D_y d, D_x d) with Neumann differences, 2 x (N2+1) x (N1+1)."""
