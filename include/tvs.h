@@ -236,6 +236,15 @@ int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_s
 size_t tvs_job_bytes(const tvs_job* job);
 int tvs_job_destroy(tvs_job* job);
 
+/* FP64 dual energies D(p^0), D(p^1), ..., D(p^S) at the start of every
+ * Schwarz sweep and after the last (S = sweeps done; the TFS dual energy of
+ * eq. tfsdualdis for Step 1, the ROF dual energy of Step 2) of the most recent
+ * tvs_step1 or tvs_step2 call on this context that asked for statistics (for
+ * tvs_schwarz_solve, of its Step 2).  *n = S + 1, or 0 if there was none;
+ * min(cap, *n) values are copied into the host array out (out may be NULL
+ * when cap is 0, to query *n).  No device work. */
+int tvs_energy_history(tvs_ctx* ctx, double* out, int cap, int* n);
+
 /* Realisation of the local projection LP_m = R P_K E of Step 1's inner
  * iterations (eqs. locglobprojpart1, locglobprojpart3), for the later
  * tvs_step1 and tvs_schwarz_solve calls of this context with more than one

@@ -235,6 +235,7 @@ struct tvs_ctx {
   std::map<tvs::GridKey, std::unique_ptr<tvs::DevBuf>> projtmp;
   tvs::KernelTimer timer;
   int lp_kind = TVS_LP_IMAGE;  // realisation of LP_m for the one-shot Step-1 calls
+  std::vector<double> history;  // energies per sweep of the last one-shot step with statistics
   tvs::DevBuf partials;  // FP64 partial sums
   tvs::DevBuf scal;      // FP64 results (energies per sweep, gap)
   size_t scal_cap = 0;
@@ -437,6 +438,7 @@ struct Step1Run {
   T *cur = nullptr, *nxt = nullptr, *zcur = nullptr, *znxt = nullptr;
   int n = 0, done = 0;
   bool finished = false;
+  std::vector<double>* hist = nullptr;  // receives D(p^0..p^done) when end() computes statistics
 
   Step1Run(Step1Problem<T>& prob, const T* d0_, int N2_, int N1_, const tvs_params* p, const tvs_layout* l,
            const tvs_iters* it, Partials pt, double* e_, KernelTimer* t)
@@ -580,6 +582,7 @@ struct Step1Run {
       st->gap = hv[its.sweeps + 1];
       if (!std::isfinite(st->energy) || !std::isfinite(st->gap))
         throw Error(TVS_ENONFINITE, "step 1: non-finite energy or gap");
+      if (hist) hist->assign(hv.begin(), hv.begin() + done + 1);
     }
   }
 };
@@ -589,6 +592,8 @@ void run_step1(tvs_ctx* c, const T* d0, int N2, int N1, const tvs_params* prm, c
                const tvs_iters* its, T* tau_out, tvs_stats* st, hipStream_t s) {
   Step1Problem<T>& P = get_step1<T>(c, N2, N1, prm->h, l, s);
   Step1Run<T> run(P, d0, N2, N1, prm, l, its, partials(c), scal(c, size_t(its->sweeps) + 3), &c->timer);
+  c->history.clear();
+  run.hist = &c->history;
   run.begin(s);
   while (run.sweep(s)) {
   }
@@ -614,6 +619,7 @@ struct Step2Run {
   T *cur = nullptr, *nxt = nullptr;
   int n = 0, done = 0;
   bool finished = false;
+  std::vector<double>* hist = nullptr;  // receives D(p^0..p^done) when end() computes statistics
 
   Step2Run(Step2Problem<T>& prob, const T* d0_, int N2_, int N1_, const tvs_params* p, const tvs_layout* l,
            const tvs_iters* it, Partials pt, double* e_, KernelTimer* t)
@@ -711,6 +717,7 @@ struct Step2Run {
       st->gap = hv[its.sweeps + 1];
       if (!std::isfinite(st->energy) || !std::isfinite(st->gap))
         throw Error(TVS_ENONFINITE, "step 2: non-finite energy or gap");
+      if (hist) hist->assign(hv.begin(), hv.begin() + done + 1);
     }
   }
 };
@@ -720,6 +727,8 @@ void run_step2(tvs_ctx* c, const T* d0, const T* tau, int N2, int N1, const tvs_
                const tvs_layout* l, const tvs_iters* its, T* d_out, tvs_stats* st, hipStream_t s) {
   Step2Problem<T>& P = get_step2<T>(c, N2, N1, prm->h, l, s);
   Step2Run<T> run(P, d0, N2, N1, prm, l, its, partials(c), scal(c, size_t(its->sweeps) + 3), &c->timer);
+  c->history.clear();
+  run.hist = &c->history;
   run.begin(tau, s);
   while (run.sweep(s)) {
   }
@@ -1293,6 +1302,15 @@ int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dty
       run_project<double>(ctx, static_cast<const double*>(u_in), n2, n1, h, static_cast<double*>(u_out), s);
     else
       throw Error(TVS_EINVAL, "unknown dtype");
+  });
+}
+
+int tvs_energy_history(tvs_ctx* ctx, double* out, int cap, int* n) {
+  return guarded([&] {
+    if (!ctx || !n) throw Error(TVS_EINVAL, "NULL argument");
+    if (cap < 0 || (cap > 0 && !out)) throw Error(TVS_EINVAL, "bad output buffer");
+    *n = static_cast<int>(ctx->history.size());
+    for (int k = 0; k < std::min(cap, *n); ++k) out[k] = ctx->history[k];
   });
 }
 

@@ -107,6 +107,8 @@ def load():
     lib.tvs_job_export_state.restype = ci
     lib.tvs_job_import_state.argtypes = [vp, vp, sz, vp, ctypes.POINTER(vp)]
     lib.tvs_job_import_state.restype = ci
+    lib.tvs_energy_history.argtypes = [vp, ctypes.POINTER(cd), ci, ctypes.POINTER(ci)]
+    lib.tvs_energy_history.restype = ci
     lib.tvs_set_local_projection.argtypes = [vp, ci]
     lib.tvs_set_local_projection.restype = ci
     lib.tvs_tangent_field.argtypes = [vp, vp, ci, ci, ci, cd, vp, vp]
@@ -124,7 +126,8 @@ EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_byte
             "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get", "tvs_job_footprint",
             "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
             "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state",
-            "tvs_tangent_field", "tvs_quality", "tvs_set_local_projection"]
+            "tvs_tangent_field", "tvs_quality", "tvs_set_local_projection",
+            "tvs_energy_history"]
 
 
 def _check(code):
@@ -282,6 +285,15 @@ class Context:
         """Advance every job in the list by one sweep of its current step."""
         arr = (ctypes.c_void_p * max(1, len(jobs)))(*[j._h.value for j in jobs])
         _check(load().tvs_batch_sweep(self._h, arr, len(jobs), _stream(self.device)))
+
+    def energy_history(self):
+        """FP64 dual energies per Schwarz sweep of the last one-shot step run
+        with statistics on this context (a list)."""
+        n = ctypes.c_int()
+        _check(load().tvs_energy_history(self._h, None, 0, ctypes.byref(n)))
+        out = (ctypes.c_double * max(1, n.value))()
+        _check(load().tvs_energy_history(self._h, out, n.value, ctypes.byref(n)))
+        return list(out[:n.value])
 
     def set_local_projection(self, kind):
         """TVS_LP_IMAGE (default) or TVS_LP_BLOCKDCT for the later one-shot
