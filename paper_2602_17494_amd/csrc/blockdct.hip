@@ -35,11 +35,12 @@ __global__ void k_bd_pack(const std::array<int, 4>* __restrict__ boxes, const T*
   D[(static_cast<size_t>(b) * amax + r) * bmax + c] = v;
 }
 
-// X[b] *= Lambda^dagger (elementwise over the n2 x n1 spectrum of every box)
+// X[b] *= Lambda^dagger (elementwise over the n2 x n1 spectrum of box
+// b = blockIdx.y)
 template <typename T>
-__global__ void k_bd_scale(T* __restrict__ X, const T* __restrict__ lam, long long plane, long long total) {
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += 256LL * gridDim.x)
-    X[i] *= lam[i % plane];
+__global__ void k_bd_scale(T* __restrict__ X, const T* __restrict__ lam, long long plane) {
+  T* x = X + blockIdx.y * plane;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < plane; i += 256LL * gridDim.x) x[i] *= lam[i];
 }
 
 // phi frame of box b = P[b] on the box
@@ -161,9 +162,9 @@ void BlockDctPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame
     TVS_BLAS(gemm_rm(handle_, false, false, n2, bmax, amax, C2, amax, sC2, D, bmax, sD, U, bmax, sU, nbox));
     // X = U C1[:,A]^T          (n2 x bmax)(bmax x n1)
     TVS_BLAS(gemm_rm(handle_, false, true, n2, n1, bmax, U, bmax, sU, C1, bmax, sC1, X, n1, sX, nbox));
-    const long long plane = (long long)n2 * n1, total = plane * nbox;
-    hipLaunchKernelGGL(k_bd_scale<T>, dim3(int(std::min<long long>(8192, (total + 255) / 256))), dim3(256), 0, s, X,
-                       lam_.as<T>(), plane, total);
+    const long long plane = (long long)n2 * n1;
+    hipLaunchKernelGGL(k_bd_scale<T>, dim3(int(std::min<long long>(1024, (plane + 255) / 256)), nbox), dim3(256), 0,
+                       s, X, lam_.as<T>(), plane);
     TVS_LAUNCH_CHECK();
     // V = C2[:,B]^T X          (amax x n2)(n2 x n1)
     TVS_BLAS(gemm_rm(handle_, true, false, amax, n1, n2, C2, amax, sC2, X, n1, sX, V, n1, sV, nbox));
