@@ -1073,13 +1073,21 @@ void job_restore(tvs_ctx* c, tvs_job* j, const StateHeader& h, const unsigned ch
   if (h.n < 0 || h.n > sweeps || h.done < 0 || h.done > sweeps || h.parity < 0 || h.parity > 1)
     throw Error(TVS_EINVAL, "state blob: run counters out of range");
   if (h.nsec != (h.step == 3 ? 3 : 5)) throw Error(TVS_EINVAL, "state blob: wrong number of sections");
+  // every section size is checked before any device work, so that a
+  // rejected blob leaves nothing queued on the stream
+  const std::vector<size_t> want =
+      h.step == 1   ? std::vector<size_t>{st.d0.bytes, st.p1->p.bytes, st.p1->va.bytes, st.p1->za.bytes, st.e1.bytes}
+      : h.step == 2 ? std::vector<size_t>{st.d0.bytes, st.tau.bytes, st.p2->p.bytes, st.p2->va.bytes, st.e2.bytes}
+                    : std::vector<size_t>{st.d0.bytes, st.tau.bytes, st.dout.bytes};
+  for (size_t k = 0; k < want.size(); ++k)
+    if (want[k] != h.sec_bytes[k])
+      throw Error(TVS_EINVAL, "state blob: section " + std::to_string(k) + " has the wrong size");
   j->st[0] = h.st[0];
   j->st[1] = h.st[1];
   if (h.step >= 2) {
     make_run2(c, j, st);
     if (h.step == 2) {
       // the Step-2 data comes from tau; the blob's tau follows d0
-      if (h.sec_bytes[1] != st.tau.bytes) throw Error(TVS_EINVAL, "state blob: tau section size mismatch");
       TVS_HIP(hipMemcpyAsync(st.tau.p, buf + sizeof h + h.sec_bytes[0], st.tau.bytes, hipMemcpyHostToDevice, s));
       st.r2->begin(st.tau.template as<T>(), s);
     }
@@ -1102,10 +1110,6 @@ void job_restore(tvs_ctx* c, tvs_job* j, const StateHeader& h, const unsigned ch
     if (h.step == 2 && h.parity != r.parity()) std::swap(r.cur, r.nxt);
   }
   const std::vector<Section> secs = state_sections<T>(j);
-  if (int(secs.size()) != h.nsec) throw Error(TVS_EINVAL, "state blob: wrong number of sections");
-  for (size_t k = 0; k < secs.size(); ++k)
-    if (secs[k].bytes != h.sec_bytes[k])
-      throw Error(TVS_EINVAL, "state blob: section " + std::to_string(k) + " has the wrong size");
   size_t off = sizeof h;
   for (const Section& sec : secs) {
     TVS_HIP(hipMemcpyAsync(sec.p, buf + off, sec.bytes, hipMemcpyHostToDevice, s));

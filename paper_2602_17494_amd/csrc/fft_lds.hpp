@@ -259,4 +259,103 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* bbuf, const Fft
   return fft_run_to_lds<T, NT>(d, in, bbuf, a, stride, batch, tw, inv);
 }
 
+// ---------------------------------------------------------------------------
+// The same passes for a transform length fixed at compile time: with the
+// radix, butterfly count, Ls and twiddle step of every pass known, the
+// butterfly and twiddle index arithmetic folds into shifts, masks and
+// full-rate 24-bit multiplies, and the sequence stride into constants.
+// Three-pass lengths only (576 = 8 * 8 * 9 is the one the plans use).  The
+// arithmetic is that of the runtime-descriptor passes; the compiler may fuse
+// multiplies and adds differently, so results can differ in the last bits.
+// ---------------------------------------------------------------------------
+template <int N, int R0, int R1, int R2>
+struct Fft3 {
+  static_assert(R0 * R1 * R2 == N, "radices must multiply to the length");
+  static constexpr int n = N;
+  template <int P> static constexpr int radix() { return P == 0 ? R0 : P == 1 ? R1 : R2; }
+  template <int P> static constexpr int ls() { return P == 0 ? 1 : P == 1 ? R0 : R0 * R1; }
+  template <int P> static constexpr int nbf() { return N / radix<P>(); }
+  template <int P> static constexpr int twstep() { return N / (ls<P>() * radix<P>()); }
+  // true if this descriptor describes the runtime plan d
+  static bool matches(const FftDesc& d) {
+    return d.n == N && d.npass == 3 && d.radix[0] == R0 && d.radix[1] == R1 && d.radix[2] == R2;
+  }
+};
+using Fft576 = Fft3<576, 8, 8, 9>;
+
+template <typename T, int STRIDE>
+struct LdsSeqS {
+  cplx<T>* p;
+  __device__ __forceinline__ cplx<T> operator()(int s, int i, int) const { return p[lds_swz(s * STRIDE + i)]; }
+  __device__ __forceinline__ void operator()(int s, int i, cplx<T> v) const { p[lds_swz(s * STRIDE + i)] = v; }
+};
+
+template <typename T, int NT, typename D, int P, typename LD, typename ST>
+__device__ __forceinline__ void fft_pass_s(LD& ld, ST& st, int batch, const cplx<T>* __restrict__ tw, bool inv) {
+  using C = cplx<T>;
+  constexpr int R = D::template radix<P>(), NBF = D::template nbf<P>(), LS = D::template ls<P>(),
+                TWS = D::template twstep<P>();
+  const int total = NBF * batch;
+  for (int jj = threadIdx.x; jj < total; jj += NT) {
+    const int b = jj / NBF;
+    const int j = jj - b * NBF;
+    const int g = j / LS;
+    const int k = j - g * LS;
+    C v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[t] = ld(b, j + t * NBF, t);
+    if constexpr (LS > 1) {
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        C w = tw[k * (t * TWS)];
+        if (inv) w.y = -w.y;
+        v[t] = cmul(v[t], w);
+      }
+    }
+    butterfly<R, T>(v, inv);
+    const int base = g * (LS * R) + k;
+#pragma unroll
+    for (int t = 0; t < R; ++t) st(b, base + t * LS, v[t]);
+  }
+}
+
+// passes 1 and 2 after pass 0 has written p0 (and a barrier): pass 1 writes
+// p1, the last pass writes through `last`
+template <typename T, int NT, typename D, typename ST>
+__device__ __forceinline__ void fft_run_tail_s(ST& last, cplx<T>* p0, cplx<T>* p1, int batch,
+                                               const cplx<T>* __restrict__ tw, bool inv) {
+  LdsSeqS<T, D::n> a{p0}, b{p1};
+  fft_pass_s<T, NT, D, 1>(a, b, batch, tw, inv);
+  __syncthreads();
+  fft_pass_s<T, NT, D, 2>(b, last, batch, tw, inv);
+}
+
+template <typename T, int NT, typename D, typename LD, typename ST>
+__device__ __forceinline__ void fft_run_s(LD& first, ST& last, cplx<T>* p0, cplx<T>* p1, int batch,
+                                          const cplx<T>* __restrict__ tw, bool inv) {
+  {
+    LdsSeqS<T, D::n> o{p0};
+    fft_pass_s<T, NT, D, 0>(first, o, batch, tw, inv);
+  }
+  __syncthreads();
+  fft_run_tail_s<T, NT, D>(last, p0, p1, batch, tw, inv);
+}
+
+// as fft_run_to_lds: the result (in p0, three passes) ends with a barrier
+template <typename T, int NT, typename D, typename LD>
+__device__ __forceinline__ cplx<T>* fft_run_to_lds_s(LD& first, cplx<T>* p0, cplx<T>* p1, int batch,
+                                                     const cplx<T>* __restrict__ tw, bool inv) {
+  LdsSeqS<T, D::n> o{p0};
+  fft_run_s<T, NT, D>(first, o, p0, p1, batch, tw, inv);
+  __syncthreads();
+  return p0;
+}
+
+template <typename T, int NT, typename D>
+__device__ __forceinline__ cplx<T>* fft_lds_s(cplx<T>* a, cplx<T>* bbuf, int batch, const cplx<T>* __restrict__ tw,
+                                              bool inv) {
+  LdsSeqS<T, D::n> in{a};
+  return fft_run_to_lds_s<T, NT, D>(in, bbuf, a, batch, tw, inv);
+}
+
 }  // namespace tvs

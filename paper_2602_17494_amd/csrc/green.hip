@@ -288,7 +288,8 @@ __device__ __forceinline__ const cplx<T>* stage_twiddles(cplx<T>* lds, const cpl
 // box) form the real and imaginary parts of one complex sequence; the half
 // spectra of the two rows are separated from the packed result and stored
 // column-major.
-template <typename T, int NT, bool TWL>
+// SL = 576: the row length is fixed at compile time (Fft576), else 0.
+template <typename T, int NT, bool TWL, int SL>
 __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
                                                        Frame uf) {
   using C = cplx<T>;
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.y;
   const GreenBox bx = d.boxes[b];
-  const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
+  const int Lj = SL ? SL : d.Lj, Lh = SL ? SL / 2 + 1 : d.Lh, ppw = d.ppw;
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
@@ -313,7 +314,11 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
     buf[lds_swz(qq * Lj + c)] = C{va, vb};
   }
   __syncthreads();
-  const C* res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
+  const C* res;
+  if constexpr (SL == Fft576::n)
+    res = fft_lds_s<T, NT, Fft576>(buf, buf + lds_round(ppw * Lj), ppw, tw, false);
+  else
+    res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
   C* S = d.S + static_cast<size_t>(b) * d.scol * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int k = d.fd_ppw.div(e), qq = e - k * ppw;
@@ -348,13 +353,13 @@ __device__ __forceinline__ cplx<T> combine_phi(cplx<T> x, cplx<T> xn, const PhiC
 
 // Column pass with the window spectra of the first inverse pass (radix R,
 // one butterfly per thread: column c, index j) loaded up front.
-template <typename T, int NT, int R, typename LD, typename ST>
+template <typename T, int NT, int R, int SL, typename LD, typename ST>
 __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, ST& st_s,
                                                 cplx<T>* bufa, cplx<T>* bufb,
                                                 const cplx<T>* const (&sp)[4], int c, int j,
                                                 bool act, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  const int Li = d.Li, cpw = d.cpw, nbf = d.fi.nbf[0].d;
+  const int Li = SL ? SL : d.Li, cpw = d.cpw, nbf = SL ? SL / R : d.fi.nbf[0].d;
   // raw values only: combining them here would wait for the loads
   C k[4][R];
 #pragma unroll
@@ -363,7 +368,11 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
 #pragma unroll
     for (int m = 0; m < 4; ++m) k[m][t] = act ? sp[m][o] : C{T(0), T(0)};
   }
-  const C* X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
+  const C* X;
+  if constexpr (SL == Fft576::n)
+    X = fft_run_to_lds_s<T, NT, Fft576>(ld_s, bufa, bufb, cpw, tw, false);
+  else
+    X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
   C* Y = (X == bufa) ? bufb : bufa;
   if (act) {
     C v[R];
@@ -378,7 +387,10 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
     for (int t = 0; t < R; ++t) Y[lds_swz(c * Li + j * R + t)] = v[t];  // Ls = 1: output j R + t
   }
   __syncthreads();
-  fft_run_tail<T, NT>(d.fi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
+  if constexpr (SL == Fft576::n)
+    fft_run_tail_s<T, NT, Fft576>(st_s, Y, const_cast<C*>(X), cpw, tw, true);
+  else
+    fft_run_tail<T, NT>(d.fi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
 }
 
 // Column transforms, spectral combination and inverse column transforms for
@@ -391,14 +403,14 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
 // tile of neighbouring boxes; boxes of one subdomain column then share an
 // XCD and its L2 for the window spectra they have in common.
 // (at most 128 VGPRs, so that four 256-thread workgroups fit on a CU)
-template <typename T, int NT, bool TWL>
+template <typename T, int NT, bool TWL, int SL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_green_cols(GreenDev<T> d) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* bufa = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
-  const int Li = d.Li, Lh = d.Lh, cpw = d.cpw, scol = d.scol;
+  const int Li = SL ? SL : d.Li, Lh = SL ? SL / 2 + 1 : d.Lh, cpw = d.cpw, scol = d.scol;
   C* bufb = bufa + lds_round(cpw * Li);
   const int k0 = blockIdx.y * cpw;
   const int ncol = min(cpw, Lh - k0);
@@ -421,18 +433,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // One butterfly per thread in the first inverse pass: its window-spectrum
     // values are loaded before the forward transform, so that their latency
     // overlaps it.
-    const int c = d.fi.nbf[0].div(threadIdx.x), j = threadIdx.x - c * nbf0;
-    const bool act = threadIdx.x < nbf0 * cpw && c < ncol;
     const cplx<T>* sp[4] = {s00, s01, s10, s11};
-    switch (r0) {
-      case 8: cols_prefetched<T, NT, 8>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-      case 9: cols_prefetched<T, NT, 9>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-      case 4: cols_prefetched<T, NT, 4>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-      case 2: cols_prefetched<T, NT, 2>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-      case 3: cols_prefetched<T, NT, 3>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-      default: cols_prefetched<T, NT, 5>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+    if constexpr (SL == Fft576::n) {
+      constexpr int nb = Fft576::nbf<0>();
+      const int c = threadIdx.x / nb, j = threadIdx.x - c * nb;
+      const bool act = threadIdx.x < nb * cpw && c < ncol;
+      cols_prefetched<T, NT, Fft576::radix<0>(), SL>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw);
+      return;
+    } else {
+      const int c = d.fi.nbf[0].div(threadIdx.x), j = threadIdx.x - c * nbf0;
+      const bool act = threadIdx.x < nbf0 * cpw && c < ncol;
+      switch (r0) {
+        case 8: cols_prefetched<T, NT, 8, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+        case 9: cols_prefetched<T, NT, 9, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+        case 4: cols_prefetched<T, NT, 4, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+        case 2: cols_prefetched<T, NT, 2, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+        case 3: cols_prefetched<T, NT, 3, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+        default: cols_prefetched<T, NT, 5, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+      }
+      return;
     }
-    return;
   }
   }
   const C* X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
@@ -446,14 +466,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   fft_run<T, NT>(d.fi, ld_phi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
 }
 
-template <typename T, int NT, bool TWL>
+template <typename T, int NT, bool TWL, int SL>
 __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restrict__ phi, Frame pf) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.y;
   const GreenBox bx = d.boxes[b];
-  const int Lj = d.Lj, Lh = d.Lh, ppw = d.ppw;
+  const int Lj = SL ? SL : d.Lj, Lh = SL ? SL / 2 + 1 : d.Lh, ppw = d.ppw;
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
@@ -475,7 +495,10 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
       if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
     }
   };
-  fft_run<T, NT>(d.fj, ld, st, buf, buf + lds_round(ppw * Lj), Lj, ppw, tw, true);
+  if constexpr (SL == Fft576::n)
+    fft_run_s<T, NT, Fft576>(ld, st, buf, buf + lds_round(ppw * Lj), ppw, tw, true);
+  else
+    fft_run<T, NT>(d.fj, ld, st, buf, buf + lds_round(ppw * Lj), Lj, ppw, tw, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -648,36 +671,43 @@ size_t GreenPlan<T>::lds_cols() const {
 template <typename T>
 template <typename F>
 void GreenPlan<T>::for_each_variant(F&& f) const {
-  auto pick = [&](auto nt_r, auto nt_c, auto twr, auto twc) {
-    f(k_green_rows_fwd<T, decltype(nt_r)::value, decltype(twr)::value>,
-      k_green_cols<T, decltype(nt_c)::value, decltype(twc)::value>,
-      k_green_rows_inv<T, decltype(nt_r)::value, decltype(twr)::value>);
+  auto pick = [&](auto nt_r, auto nt_c, auto twr, auto twc, auto sl) {
+    f(k_green_rows_fwd<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value>,
+      k_green_cols<T, decltype(nt_c)::value, decltype(twc)::value, decltype(sl)::value>,
+      k_green_rows_inv<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value>);
   };
   using S = std::integral_constant<int, kFftThreads>;
   using L = std::integral_constant<int, kFftThreadsLong>;
   using Y = std::true_type;
   using N = std::false_type;
+  using G = std::integral_constant<int, 0>;
   const bool rs = nt_rows_ == kFftThreads, cs = nt_cols_ == kFftThreads;
+  // the 576-point boxes of 256-point subdomain cores with 1024-thread row and
+  // 256-thread column workgroups, twiddles in LDS: the compile-time passes
+  if (!rs && cs && twl_rows_ && twl_cols_ && Fft576::matches(dev_.fi) && Fft576::matches(dev_.fj)) {
+    pick(L{}, S{}, Y{}, Y{}, std::integral_constant<int, Fft576::n>{});
+    return;
+  }
   if (rs && cs) {
-    if (twl_rows_ && twl_cols_) pick(S{}, S{}, Y{}, Y{});
-    else if (twl_rows_) pick(S{}, S{}, Y{}, N{});
-    else if (twl_cols_) pick(S{}, S{}, N{}, Y{});
-    else pick(S{}, S{}, N{}, N{});
+    if (twl_rows_ && twl_cols_) pick(S{}, S{}, Y{}, Y{}, G{});
+    else if (twl_rows_) pick(S{}, S{}, Y{}, N{}, G{});
+    else if (twl_cols_) pick(S{}, S{}, N{}, Y{}, G{});
+    else pick(S{}, S{}, N{}, N{}, G{});
   } else if (rs) {
-    if (twl_rows_ && twl_cols_) pick(S{}, L{}, Y{}, Y{});
-    else if (twl_rows_) pick(S{}, L{}, Y{}, N{});
-    else if (twl_cols_) pick(S{}, L{}, N{}, Y{});
-    else pick(S{}, L{}, N{}, N{});
+    if (twl_rows_ && twl_cols_) pick(S{}, L{}, Y{}, Y{}, G{});
+    else if (twl_rows_) pick(S{}, L{}, Y{}, N{}, G{});
+    else if (twl_cols_) pick(S{}, L{}, N{}, Y{}, G{});
+    else pick(S{}, L{}, N{}, N{}, G{});
   } else if (cs) {
-    if (twl_rows_ && twl_cols_) pick(L{}, S{}, Y{}, Y{});
-    else if (twl_rows_) pick(L{}, S{}, Y{}, N{});
-    else if (twl_cols_) pick(L{}, S{}, N{}, Y{});
-    else pick(L{}, S{}, N{}, N{});
+    if (twl_rows_ && twl_cols_) pick(L{}, S{}, Y{}, Y{}, G{});
+    else if (twl_rows_) pick(L{}, S{}, Y{}, N{}, G{});
+    else if (twl_cols_) pick(L{}, S{}, N{}, Y{}, G{});
+    else pick(L{}, S{}, N{}, N{}, G{});
   } else {
-    if (twl_rows_ && twl_cols_) pick(L{}, L{}, Y{}, Y{});
-    else if (twl_rows_) pick(L{}, L{}, Y{}, N{});
-    else if (twl_cols_) pick(L{}, L{}, N{}, Y{});
-    else pick(L{}, L{}, N{}, N{});
+    if (twl_rows_ && twl_cols_) pick(L{}, L{}, Y{}, Y{}, G{});
+    else if (twl_rows_) pick(L{}, L{}, Y{}, N{}, G{});
+    else if (twl_cols_) pick(L{}, L{}, N{}, Y{}, G{});
+    else pick(L{}, L{}, N{}, N{}, G{});
   }
 }
 

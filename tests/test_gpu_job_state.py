@@ -157,5 +157,13 @@ def test_malformed_blobs_rejected(ctx):
     rejected(bad)
     bad = blob.copy(); bad[24] = 7           # dtype
     rejected(bad)
+    # section sizes that add up but do not match the job's arrays (the
+    # section table is the last 48 bytes of the header)
+    hb = int(blob[12:16].view(np.uint32)[0])
+    bad = blob.copy()
+    sec = bad[hb - 48:hb].view(np.uint64)
+    sec[1] += 8
+    sec[2] -= 8
+    rejected(bad)
     # the intact blob still resumes
     ctx.import_job(blob).close()

@@ -76,6 +76,7 @@ CASES = [
     (100, 131, (4, 4, 6, 6), 2, 2),
     (150, 200, (2, 2, 6, 8), 2, 2),   # frames wider than 64 columns (padded pitch)
     (90, 140, (1, 1, 0, 0), 2, 3),    # single domain, padded pitch
+    (544, 544, (2, 2, 8, 8), 1, 3),   # 277-point Green boxes: 576-point transforms (compile-time passes)
 ]
 
 
