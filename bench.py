@@ -22,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -254,13 +255,27 @@ def calibrate_copy():
     print(json.dumps({"calibration": "copy", "bytes_read": n * 4, "bytes_written": n * 4}), flush=True)
 
 
-def kernel_source_hash():
+def _code_only(text):
+    """C++ source without comments and blank space, so that editing a comment
+    does not invalidate measurements taken on the same code."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(csrc=None, read=None):
+    """Hash of the HIP sources' code (comments and spacing ignored)."""
+    csrc = csrc or os.path.join(ROOT, "paper_2602_17494_amd", "csrc")
+    names = sorted(os.listdir(csrc)) if read is None else sorted(read)
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2602_17494_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
+    for name in names:
+        if read is None:
+            with open(os.path.join(csrc, name), encoding="utf-8") as f:
+                text = f.read()
+        else:
+            text = read[name]
+        h.update(name.encode())
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

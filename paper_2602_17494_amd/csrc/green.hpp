@@ -94,7 +94,8 @@ class GreenPlan {
   // support, and div uses the grid's boundary rules (Section 4.1).
   void apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t stream,
                  KernelTimer* timer = nullptr, const char* tag = "green");
-  // algorithmic bytes of one launch of each pass
+  // algorithmic bytes of one launch of each pass (the minimum HBM traffic
+  // it must move: its inputs read once, its outputs written once)
   double bytes_rows_fwd() const, bytes_cols() const, bytes_rows_inv() const;
 
   int n2, n1, nbox, Li, Lj;
