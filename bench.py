@@ -294,6 +294,24 @@ def read_traffic(kernel):
     return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
+def read_valu_issue(kernel):
+    """VALU instruction-issue time per launch of `kernel` (timer name) from the
+    committed rocprofv3 SQ counters, or None when missing or taken on other
+    code: SQ_INSTS_VALU * 4 cycles over the 1024 SIMDs at 2.4 GHz, the time
+    the kernel needs for its vector instructions alone."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            name = json.load(f)["kernels"][kernel]["kernel"]
+        with open(os.path.join(ROOT, "profiles", "sq_counters.json")) as f:
+            rec = json.load(f)
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(name)
+    return None if ent is None else ent.get("valu_issue_us")
+
+
 def cpu_baseline(n, sigma, lay):
     """Time the FP64 oracle on a bounded sample of the workload: one
     subdomain's inner loop of each step (Algorithm 5 for Step 1, Algorithm 3
@@ -399,6 +417,7 @@ def main():
     dname, (dlaunch, dms, dbytes) = dom
     achieved = (dbytes / dlaunch) / (dms / dlaunch * 1e-3) / 1e9
     traffic = read_traffic(dname)
+    valu_us = read_valu_issue(dname)
     breakdown = {k: {"timed_launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2) if v[0] else None,
                      "gbs": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                  for k, v in sorted(timing.items(), key=lambda kv: -kv[1][1])}
@@ -438,7 +457,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": dbytes / dlaunch,
-                     "avg_launch_us": round(dms / dlaunch * 1e3, 2)},
+                     "avg_launch_us": round(dms / dlaunch * 1e3, 2),
+                     "valu_issue_us": valu_us,
+                     "valu_issue_frac": None if valu_us is None else round(valu_us / (dms / dlaunch * 1e3), 3)},
         "kernels": breakdown,
     }
 
