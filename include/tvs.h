@@ -176,7 +176,8 @@ int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dty
  *                      kernel classes (>= 0), or a negative error code
  *   tvs_timing_get     entry i (0 <= i < count): class name copied into
  *                      name[name_len], launches, total milliseconds, total
- *                      algorithmic bytes */
+ *                      algorithmic bytes (for the class "s1_bdct" of the
+ *                      block-DCT local projection: floating-point operations) */
 int tvs_timing_enable(tvs_ctx* ctx, int enable);
 int tvs_timing_reset(tvs_ctx* ctx);
 int tvs_timing_count(tvs_ctx* ctx);
@@ -184,7 +185,8 @@ int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* lau
                    double* bytes);
 
 /* Jobs: one image's Step 1 + Step 2 solve (the same problem and the same
- * computation as tvs_schwarz_solve, whose results it reproduces bit for bit)
+ * computation as tvs_schwarz_solve with the default TVS_LP_IMAGE local
+ * projection, whose results it reproduces bit for bit)
  * with its own device state, resident between calls: the problem's plans,
  * the dual variables of every subdomain, a copy of d0, tau and d.  A job is
  * advanced one Schwarz sweep (Algorithm 2) at a time, so that a caller can
