@@ -416,8 +416,10 @@ def main():
     dom = max(timing.items(), key=lambda kv: kv[1][1])
     dname, (dlaunch, dms, dbytes) = dom
     achieved = (dbytes / dlaunch) / (dms / dlaunch * 1e-3) / 1e9
-    traffic = read_traffic(dname)
-    valu_us = read_valu_issue(dname)
+    # the committed counters were taken on the default workload only
+    profiled = (n == 2048 and list(args.layout) == [8, 8, 16, 16])
+    traffic = read_traffic(dname) if profiled else None
+    valu_us = read_valu_issue(dname) if profiled else None
     breakdown = {k: {"timed_launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2) if v[0] else None,
                      "gbs": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                  for k, v in sorted(timing.items(), key=lambda kv: -kv[1][1])}
