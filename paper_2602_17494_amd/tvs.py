@@ -313,6 +313,8 @@ class Context:
         """{"psnr", "mssim", "mse"} of x against ref (same shape and dtype)."""
         if x.dim() != 2:
             raise ValueError("expected a 2-D array")
+        if x.shape != ref.shape:
+            raise ValueError("x and ref must have the same shape")
         n2, n1 = x.shape
         out = (ctypes.c_double * 3)()
         _check(load().tvs_quality(self._h, _dev(x, (n2, n1)), _dev(ref, (n2, n1), x.dtype), n2, n1,

@@ -107,3 +107,11 @@ def test_jobs_keep_the_image_method(ctxs):
     torch.cuda.synchronize()
     assert torch.equal(d_job, d_im)
     job.close()
+
+
+def test_unknown_local_projection_rejected(ctxs):
+    from paper_2602_17494_amd import TvsError
+    bd, _ = ctxs
+    with pytest.raises(TvsError) as e:
+        bd.set_local_projection(7)
+    assert e.value.code == -1  # TVS_EINVAL

@@ -159,3 +159,13 @@ def test_experiment_end_to_end(ctx, images):
     assert all(r["sweeps"] >= 1 for r in res["tfs"]["rows"] + res["irv2"]["rows"] + res["irv1"]["rows"])
     # denoising helps: the best reconstruction beats the noisy observation
     assert res["irv2"]["best_psnr"]["psnr"] > res["noisy"]["psnr"] + 3.0
+
+
+def test_quality_argument_errors(ctx):
+    a = torch.zeros((4, 5), dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        ctx.quality(a, torch.zeros((4, 6), dtype=torch.float64, device=DEV))
+    with pytest.raises(TypeError):
+        ctx.quality(a, torch.zeros((4, 5), dtype=torch.float32, device=DEV))
+    with pytest.raises(ValueError):
+        ctx.quality(torch.zeros(5, dtype=torch.float64, device=DEV), torch.zeros(5, dtype=torch.float64, device=DEV))
