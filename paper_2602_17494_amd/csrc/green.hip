@@ -288,6 +288,10 @@ __device__ __forceinline__ const cplx<T>* stage_twiddles(cplx<T>* lds, const cpl
 // box) form the real and imaginary parts of one complex sequence; the half
 // spectra of the two rows are separated from the packed result and stored
 // column-major.
+// Column stride of the half spectra for 576-point plans: boxes of 271-288
+// rows, rounded up to 32 and padded by 16 (as the plan computes it).
+constexpr int kScol576 = 304;
+
 // SL = 576: the row length is fixed at compile time (Fft576), else 0.
 template <typename T, int NT, bool TWL, int SL>
 __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
@@ -319,13 +323,14 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
     res = fft_lds_s<T, NT, Fft576>(buf, buf + lds_round(ppw * Lj), ppw, tw, false);
   else
     res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
-  C* S = d.S + static_cast<size_t>(b) * d.scol * Lh;
+  const int scol = SL ? kScol576 : d.scol;
+  C* S = d.S + static_cast<size_t>(b) * scol * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int k = d.fd_ppw.div(e), qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const C z = res[lds_swz(qq * Lj + k)];
     const C zn = res[lds_swz(qq * Lj + (k == 0 ? 0 : Lj - k))];
-    C* col = S + static_cast<size_t>(k) * d.scol;
+    C* col = S + static_cast<size_t>(k) * scol;
     if (ra < bx.ni) col[ra] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
     if (rb < bx.ni) col[rb] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
   }
@@ -410,7 +415,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   C* bufa = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
-  const int Li = SL ? SL : d.Li, Lh = SL ? SL / 2 + 1 : d.Lh, cpw = d.cpw, scol = d.scol;
+  const int Li = SL ? SL : d.Li, Lh = SL ? SL / 2 + 1 : d.Lh, cpw = d.cpw, scol = SL ? kScol576 : d.scol;
   C* bufb = bufa + lds_round(cpw * Li);
   const int k0 = blockIdx.y * cpw;
   const int ncol = min(cpw, Lh - k0);
@@ -427,43 +432,45 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   auto st_s = [&](int c, int r, C v) {
     if (c < ncol && r < bx.ni) S[c * scol + r] = v;
   };
-  if constexpr (sizeof(T) == 4) {
-  const int r0 = d.fi.radix[0], nbf0 = d.fi.nbf[0].d;
-  if (d.fi.npass >= 2 && nbf0 * cpw <= NT) {
-    // One butterfly per thread in the first inverse pass: its window-spectrum
-    // values are loaded before the forward transform, so that their latency
-    // overlaps it.
+  if constexpr (sizeof(T) == 4 && SL == Fft576::n) {
+    // One butterfly per thread in the first inverse pass (the plan selects
+    // this variant only when cpw * 72 <= NT): its window-spectrum values are
+    // loaded before the forward transform, so that their latency overlaps it.
     const cplx<T>* sp[4] = {s00, s01, s10, s11};
-    if constexpr (SL == Fft576::n) {
-      constexpr int nb = Fft576::nbf<0>();
-      const int c = threadIdx.x / nb, j = threadIdx.x - c * nb;
-      const bool act = threadIdx.x < nb * cpw && c < ncol;
-      cols_prefetched<T, NT, Fft576::radix<0>(), SL>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw);
-      return;
-    } else {
-      const int c = d.fi.nbf[0].div(threadIdx.x), j = threadIdx.x - c * nbf0;
-      const bool act = threadIdx.x < nbf0 * cpw && c < ncol;
-      switch (r0) {
-        case 8: cols_prefetched<T, NT, 8, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-        case 9: cols_prefetched<T, NT, 9, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-        case 4: cols_prefetched<T, NT, 4, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-        case 2: cols_prefetched<T, NT, 2, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-        case 3: cols_prefetched<T, NT, 3, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
-        default: cols_prefetched<T, NT, 5, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+    constexpr int nb = Fft576::nbf<0>();
+    const int c = threadIdx.x / nb, j = threadIdx.x - c * nb;
+    const bool act = threadIdx.x < nb * cpw && c < ncol;
+    cols_prefetched<T, NT, Fft576::radix<0>(), SL>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw);
+    return;
+  } else {
+    if constexpr (sizeof(T) == 4) {
+      const int r0 = d.fi.radix[0], nbf0 = d.fi.nbf[0].d;
+      if (d.fi.npass >= 2 && nbf0 * cpw <= NT) {
+        // as above, with the runtime descriptor
+        const cplx<T>* sp[4] = {s00, s01, s10, s11};
+        const int c = d.fi.nbf[0].div(threadIdx.x), j = threadIdx.x - c * nbf0;
+        const bool act = threadIdx.x < nbf0 * cpw && c < ncol;
+        switch (r0) {
+          case 8: cols_prefetched<T, NT, 8, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+          case 9: cols_prefetched<T, NT, 9, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+          case 4: cols_prefetched<T, NT, 4, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+          case 2: cols_prefetched<T, NT, 2, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+          case 3: cols_prefetched<T, NT, 3, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+          default: cols_prefetched<T, NT, 5, 0>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw); break;
+        }
+        return;
       }
-      return;
     }
+    const C* X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
+    C* Y = (X == bufa) ? bufb : bufa;
+    auto ld_phi = [&](int c, int ki, int) -> C {
+      if (c >= ncol) return C{T(0), T(0)};
+      const int o = c * Li + ki;
+      return combine_phi(X[lds_swz(o)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))],
+                         phi_coef(s00[o], s01[o], s10[o], s11[o]));
+    };
+    fft_run<T, NT>(d.fi, ld_phi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
   }
-  }
-  const C* X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
-  C* Y = (X == bufa) ? bufb : bufa;
-  auto ld_phi = [&](int c, int ki, int) -> C {
-    if (c >= ncol) return C{T(0), T(0)};
-    const int o = c * Li + ki;
-    return combine_phi(X[lds_swz(o)], X[lds_swz(c * Li + (ki == 0 ? 0 : Li - ki))],
-                       phi_coef(s00[o], s01[o], s10[o], s11[o]));
-  };
-  fft_run<T, NT>(d.fi, ld_phi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
 }
 
 template <typename T, int NT, bool TWL, int SL>
@@ -477,12 +484,13 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
-  const C* S = d.S + static_cast<size_t>(b) * d.scol * Lh;
+  const int scol = SL ? kScol576 : d.scol;
+  const C* S = d.S + static_cast<size_t>(b) * scol * Lh;
   const int half = Lj / 2;
   auto ld = [&](int qq, int k, int) -> C {
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     const int kk = k <= half ? k : Lj - k;
-    const C* col = S + static_cast<size_t>(kk) * d.scol;
+    const C* col = S + static_cast<size_t>(kk) * scol;
     const C a = ra < bx.ni ? col[ra] : C{T(0), T(0)};
     const C c = rb < bx.ni ? col[rb] : C{T(0), T(0)};
     return k <= half ? C{a.x - c.y, a.y + c.x} : C{a.x + c.y, c.x - a.y};
@@ -684,7 +692,8 @@ void GreenPlan<T>::for_each_variant(F&& f) const {
   const bool rs = nt_rows_ == kFftThreads, cs = nt_cols_ == kFftThreads;
   // the 576-point boxes of 256-point subdomain cores with 1024-thread row and
   // 256-thread column workgroups, twiddles in LDS: the compile-time passes
-  if (!rs && cs && twl_rows_ && twl_cols_ && Fft576::matches(dev_.fi) && Fft576::matches(dev_.fj)) {
+  if (!rs && cs && twl_rows_ && twl_cols_ && Fft576::matches(dev_.fi) && Fft576::matches(dev_.fj) &&
+      dev_.scol == kScol576 && dev_.cpw * Fft576::nbf<0>() <= kFftThreads) {
     pick(L{}, S{}, Y{}, Y{}, std::integral_constant<int, Fft576::n>{});
     return;
   }
