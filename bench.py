@@ -139,19 +139,23 @@ def serve_mode(args):
         specs.append((k, n, sigma, m))
     imgs = {}
     for k, n, sigma, m in specs:
-        _, d64 = synth.noisy_f32(n, n, sigma, 5000 + k)
-        imgs[k] = d64
-    # plain FP64 capacity: time each request's plain solve (warm plans first)
+        imgs[k], _ = synth.noisy_f32(n, n, sigma, 5000 + k)
+    # plain FP64 capacity: time each request's plain solve (warm plans first),
+    # each in a context of its own so that plans of many sizes are not kept
     plain_t = {}
-    for k, n, sigma, m in specs:
+    for i, (k, n, sigma, m) in enumerate(specs):
         delta, alpha = synth.params_for_sigma(sigma)
         d0 = torch.tensor(imgs[k], dtype=torch.float64, device="cuda:0")
-        ctx.schwarz_solve(d0, make_params(delta, alpha), make_layout(), make_iters(1, 1), stats=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.schwarz_solve(d0, make_params(delta, alpha), make_layout(), its_plain, stats=False)
-        torch.cuda.synchronize()
-        plain_t[k] = time.perf_counter() - t0
+        with Context(0) as pc:
+            pc.schwarz_solve(d0, make_params(delta, alpha), make_layout(), make_iters(1, 1), stats=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc.schwarz_solve(d0, make_params(delta, alpha), make_layout(), its_plain, stats=False)
+            torch.cuda.synchronize()
+            plain_t[k] = time.perf_counter() - t0
+        if (i + 1) % 50 == 0:
+            print(f"serve: plain FP64 service times measured for {i + 1} of {len(specs)} requests",
+                  file=sys.stderr, flush=True)
     mean_service = float(np.mean(list(plain_t.values())))
     rate = 0.7 / mean_service
     arrivals, t = [], 0.0
@@ -171,7 +175,9 @@ def serve_mode(args):
         lay = make_layout(m, m, 16 if m > 1 else 0, 16 if m > 1 else 0)
         reqs.append(Request(k, d0, make_params(delta, alpha), lay, its, arrival=a))
     t0 = time.perf_counter()
-    results, srv = serve(ctx, reqs, 64 << 30)
+    results, srv = serve(ctx, reqs, 64 << 30,
+                         progress=lambda done: print(f"serve: {done} of {len(reqs)} requests served",
+                                                     file=sys.stderr, flush=True))
     wall = time.perf_counter() - t0
     pix = sum(((n + 1) ** 2 + n * n) for _, n, _, _ in specs) * 10 * 100
     lat = latency_summary(results)

@@ -76,12 +76,12 @@ class Server:
             return []
         self.ctx.batch_sweep([job for _, job, _ in self.live])
         self.rounds += 1
-        torch.cuda.current_stream(self.ctx.device).synchronize()
+        self.ctx.synchronize()
         out, keep = [], []
         for req, job, adm in self.live:
             if job.done:
                 d, tau, st = job.result()
-                torch.cuda.current_stream(self.ctx.device).synchronize()
+                self.ctx.synchronize()
                 out.append(Result(req.rid, d, tau, st, req.arrival, adm, now_fn()))
                 job.close()
                 self.in_use -= req.footprint
@@ -91,10 +91,11 @@ class Server:
         return out
 
 
-def serve(ctx, requests, budget, clock=time.perf_counter):
+def serve(ctx, requests, budget, clock=time.perf_counter, progress=None, every=50):
     """Run `requests` (with arrival offsets in seconds) through a server
     with the given byte budget in real time; returns the results in
-    completion order and the server (for its counters)."""
+    completion order and the server (for its counters).  progress, if
+    given, is called with the number of finished requests every `every`."""
     pending = sorted(requests, key=lambda r: r.arrival)
     srv = Server(ctx, budget)
     t0 = clock()
@@ -106,7 +107,10 @@ def serve(ctx, requests, budget, clock=time.perf_counter):
         if not srv.queue and not srv.live:
             time.sleep(max(0.0, min(0.01, pending[0].arrival - now())))
             continue
+        before = len(done)
         done.extend(srv.round(now))
+        if progress and len(done) // every > before // every:
+            progress(len(done))
     return done, srv
 
 

@@ -201,6 +201,10 @@ class Context:
     def bytes(self):
         return int(load().tvs_ctx_bytes(self._h))
 
+    def synchronize(self):
+        """Wait for the work enqueued on the device's current stream."""
+        torch.cuda.current_stream(self.device).synchronize()
+
     def step1(self, d0, params, layout, iters, tau_out=None, stats=True):
         n2, n1 = d0.shape
         if tau_out is None:
