@@ -261,6 +261,29 @@ def calibrate_copy():
     print(json.dumps({"calibration": "copy", "bytes_read": n * 4, "bytes_written": n * 4}), flush=True)
 
 
+def copy_bandwidth():
+    """HBM bandwidth a plain device copy reaches on this GPU (1 GiB read and
+    1 GiB written per copy, best of 5, HIP events on the current stream):
+    the practical ceiling next to the 8 TB/s published peak."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2 * n * 4 / (best * 1e-3) / 1e9
+
+
 def _code_only(text):
     """C++ source without comments and blank space, so that editing a comment
     does not invalidate measurements taken on the same code."""
@@ -467,7 +490,8 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": dbytes / dlaunch,
                      "avg_launch_us": round(dms / dlaunch * 1e3, 2),
                      "valu_issue_us": valu_us,
-                     "valu_issue_frac": None if valu_us is None else round(valu_us / (dms / dlaunch * 1e3), 3)},
+                     "valu_issue_frac": None if valu_us is None else round(valu_us / (dms / dlaunch * 1e3), 3),
+                     "copy_gbs": round(copy_bandwidth(), 1)},
         "kernels": breakdown,
     }
 
