@@ -11,6 +11,8 @@
 // convention and are unnormalised; the inverse uses exp(+...).
 #pragma once
 
+#include <type_traits>
+
 #include "tvs_internal.hpp"
 
 namespace tvs {
@@ -264,7 +266,8 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* bbuf, const Fft
 // radix, butterfly count, Ls and twiddle step of every pass known, the
 // butterfly and twiddle index arithmetic folds into shifts, masks and
 // full-rate 24-bit multiplies, and the sequence stride into constants.
-// Three-pass lengths only (576 = 8 * 8 * 9 is the one the plans use).  The
+// Three-pass lengths only (512 = 8 * 8 * 8, 576 = 8 * 8 * 9 and
+// 648 = 8 * 9 * 9, with the radices in the plans' order).  The
 // arithmetic is that of the runtime-descriptor passes; the compiler may fuse
 // multiplies and adds differently, so results can differ in the last bits.
 // ---------------------------------------------------------------------------
@@ -281,7 +284,12 @@ struct Fft3 {
     return d.n == N && d.npass == 3 && d.radix[0] == R0 && d.radix[1] == R1 && d.radix[2] == R2;
   }
 };
+using Fft512 = Fft3<512, 8, 8, 8>;
 using Fft576 = Fft3<576, 8, 8, 9>;
+using Fft648 = Fft3<648, 8, 9, 9>;
+// the compile-time descriptor of a length (SL = 512, 576 or 648)
+template <int SL>
+using FftOf = std::conditional_t<SL == 512, Fft512, std::conditional_t<SL == 576, Fft576, Fft648>>;
 
 template <typename T, int STRIDE>
 struct LdsSeqS {

@@ -288,11 +288,14 @@ __device__ __forceinline__ const cplx<T>* stage_twiddles(cplx<T>* lds, const cpl
 // box) form the real and imaginary parts of one complex sequence; the half
 // spectra of the two rows are separated from the packed result and stored
 // column-major.
-// Column stride of the half spectra for 576-point plans: boxes of 271-288
-// rows, rounded up to 32 and padded by 16 (as the plan computes it).
-constexpr int kScol576 = 304;
+// Column stride of the half spectra for the compile-time lengths: the box
+// rows a length of this size serves (251-256, 271-288, 321-324: the next
+// smaller smooth lengths are 500, 540 and 640), rounded up to 32 and padded
+// by 16, as the plan computes it; the plan checks it before choosing them.
+constexpr int scol_of(int sl) { return sl == 512 ? 272 : sl == 576 ? 304 : 368; }
 
-// SL = 576: the row length is fixed at compile time (Fft576), else 0.
+// SL = 512, 576 or 648: the transform length is fixed at compile time
+// (FftOf<SL>), else 0.
 template <typename T, int NT, bool TWL, int SL>
 __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
                                                        Frame uf) {
@@ -319,11 +322,11 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   }
   __syncthreads();
   const C* res;
-  if constexpr (SL == Fft576::n)
-    res = fft_lds_s<T, NT, Fft576>(buf, buf + lds_round(ppw * Lj), ppw, tw, false);
+  if constexpr (SL != 0)
+    res = fft_lds_s<T, NT, FftOf<SL>>(buf, buf + lds_round(ppw * Lj), ppw, tw, false);
   else
     res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
-  const int scol = SL ? kScol576 : d.scol;
+  const int scol = SL ? scol_of(SL) : d.scol;
   C* S = d.S + static_cast<size_t>(b) * scol * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int k = d.fd_ppw.div(e), qq = e - k * ppw;
@@ -374,8 +377,8 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
     for (int m = 0; m < 4; ++m) k[m][t] = act ? sp[m][o] : C{T(0), T(0)};
   }
   const C* X;
-  if constexpr (SL == Fft576::n)
-    X = fft_run_to_lds_s<T, NT, Fft576>(ld_s, bufa, bufb, cpw, tw, false);
+  if constexpr (SL != 0)
+    X = fft_run_to_lds_s<T, NT, FftOf<SL>>(ld_s, bufa, bufb, cpw, tw, false);
   else
     X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
   C* Y = (X == bufa) ? bufb : bufa;
@@ -392,8 +395,8 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
     for (int t = 0; t < R; ++t) Y[lds_swz(c * Li + j * R + t)] = v[t];  // Ls = 1: output j R + t
   }
   __syncthreads();
-  if constexpr (SL == Fft576::n)
-    fft_run_tail_s<T, NT, Fft576>(st_s, Y, const_cast<C*>(X), cpw, tw, true);
+  if constexpr (SL != 0)
+    fft_run_tail_s<T, NT, FftOf<SL>>(st_s, Y, const_cast<C*>(X), cpw, tw, true);
   else
     fft_run_tail<T, NT>(d.fi, st_s, Y, const_cast<C*>(X), Li, cpw, tw, true);
 }
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   C* bufa = reinterpret_cast<C*>(smem_raw);
   const int b = blockIdx.x;
   const GreenBox bx = d.boxes[b];
-  const int Li = SL ? SL : d.Li, Lh = SL ? SL / 2 + 1 : d.Lh, cpw = d.cpw, scol = SL ? kScol576 : d.scol;
+  const int Li = SL ? SL : d.Li, Lh = SL ? SL / 2 + 1 : d.Lh, cpw = d.cpw, scol = SL ? scol_of(SL) : d.scol;
   C* bufb = bufa + lds_round(cpw * Li);
   const int k0 = blockIdx.y * cpw;
   const int ncol = min(cpw, Lh - k0);
@@ -432,15 +435,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   auto st_s = [&](int c, int r, C v) {
     if (c < ncol && r < bx.ni) S[c * scol + r] = v;
   };
-  if constexpr (sizeof(T) == 4 && SL == Fft576::n) {
+  if constexpr (sizeof(T) == 4 && SL != 0) {
     // One butterfly per thread in the first inverse pass (the plan selects
     // this variant only when cpw * 72 <= NT): its window-spectrum values are
     // loaded before the forward transform, so that their latency overlaps it.
     const cplx<T>* sp[4] = {s00, s01, s10, s11};
-    constexpr int nb = Fft576::nbf<0>();
+    constexpr int nb = FftOf<SL>::template nbf<0>();
     const int c = threadIdx.x / nb, j = threadIdx.x - c * nb;
     const bool act = threadIdx.x < nb * cpw && c < ncol;
-    cols_prefetched<T, NT, Fft576::radix<0>(), SL>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw);
+    cols_prefetched<T, NT, FftOf<SL>::template radix<0>(), SL>(d, ld_s, st_s, bufa, bufb, sp, c, j, act, tw);
     return;
   } else {
     if constexpr (sizeof(T) == 4) {
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   const int q0 = blockIdx.x * ppw;
   if (2 * q0 >= bx.ni) return;
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
-  const int scol = SL ? kScol576 : d.scol;
+  const int scol = SL ? scol_of(SL) : d.scol;
   const C* S = d.S + static_cast<size_t>(b) * scol * Lh;
   const int half = Lj / 2;
   auto ld = [&](int qq, int k, int) -> C {
@@ -503,8 +506,8 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
       if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
     }
   };
-  if constexpr (SL == Fft576::n)
-    fft_run_s<T, NT, Fft576>(ld, st, buf, buf + lds_round(ppw * Lj), ppw, tw, true);
+  if constexpr (SL != 0)
+    fft_run_s<T, NT, FftOf<SL>>(ld, st, buf, buf + lds_round(ppw * Lj), ppw, tw, true);
   else
     fft_run<T, NT>(d.fj, ld, st, buf, buf + lds_round(ppw * Lj), Lj, ppw, tw, true);
 }
@@ -690,12 +693,18 @@ void GreenPlan<T>::for_each_variant(F&& f) const {
   using N = std::false_type;
   using G = std::integral_constant<int, 0>;
   const bool rs = nt_rows_ == kFftThreads, cs = nt_cols_ == kFftThreads;
-  // the 576-point boxes of 256-point subdomain cores with 1024-thread row and
-  // 256-thread column workgroups, twiddles in LDS: the compile-time passes
-  if (!rs && cs && twl_rows_ && twl_cols_ && Fft576::matches(dev_.fi) && Fft576::matches(dev_.fj) &&
-      dev_.scol == kScol576 && dev_.cpw * Fft576::nbf<0>() <= kFftThreads) {
-    pick(L{}, S{}, Y{}, Y{}, std::integral_constant<int, Fft576::n>{});
-    return;
+  // square 512-, 576- or 648-point boxes (the 576-point ones come from
+  // 256-point subdomain cores) with 1024-thread row and 256-thread column
+  // workgroups, twiddles in LDS: the compile-time passes
+  if (!rs && cs && twl_rows_ && twl_cols_ && Li == Lj) {
+    auto fits = [&](auto desc) {
+      using D = decltype(desc);
+      return D::matches(dev_.fi) && D::matches(dev_.fj) && dev_.scol == scol_of(D::n) &&
+             dev_.cpw * D::template nbf<0>() <= kFftThreads;
+    };
+    if (Li == 512 && fits(Fft512{})) return pick(L{}, S{}, Y{}, Y{}, std::integral_constant<int, 512>{});
+    if (Li == 576 && fits(Fft576{})) return pick(L{}, S{}, Y{}, Y{}, std::integral_constant<int, 576>{});
+    if (Li == 648 && fits(Fft648{})) return pick(L{}, S{}, Y{}, Y{}, std::integral_constant<int, 648>{});
   }
   if (rs && cs) {
     if (twl_rows_ && twl_cols_) pick(S{}, S{}, Y{}, Y{}, G{});

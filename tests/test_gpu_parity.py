@@ -77,6 +77,8 @@ CASES = [
     (150, 200, (2, 2, 6, 8), 2, 2),   # frames wider than 64 columns (padded pitch)
     (90, 140, (1, 1, 0, 0), 2, 3),    # single domain, padded pitch
     (544, 544, (2, 2, 8, 8), 1, 3),   # 277-point Green boxes: 576-point transforms (compile-time passes)
+    (496, 496, (2, 2, 8, 8), 1, 3),   # 254-point boxes: 512-point transforms (compile-time passes)
+    (632, 632, (2, 2, 8, 8), 1, 2),   # 322-point boxes: 648-point transforms (compile-time passes)
 ]
 
 
