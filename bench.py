@@ -292,10 +292,16 @@ def _code_only(text):
     return " ".join(text.split())
 
 
+# the host orchestration (api.hip) launches the kernels but holds none of them
+HOST_ONLY_SOURCES = {"api.hip"}
+
+
 def kernel_source_hash(csrc=None, read=None):
-    """Hash of the HIP sources' code (comments and spacing ignored)."""
+    """Hash of the code of the HIP sources that hold kernels (comments and
+    spacing ignored)."""
     csrc = csrc or os.path.join(ROOT, "paper_2602_17494_amd", "csrc")
     names = sorted(os.listdir(csrc)) if read is None else sorted(read)
+    names = [n for n in names if n not in HOST_ONLY_SOURCES]
     h = hashlib.sha256()
     for name in names:
         if read is None:

@@ -213,14 +213,18 @@ int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* lau
  *                      job's work) and sets up Step 2; the one that completes
  *                      Step 2 computes d.  A finished job is left as it is.
  *                      Jobs share no data: neither the order of the list nor
- *                      the overlap changes any result.
- *   tvs_job_status     step 1 or 2 (3 when finished), sweeps done in it,
- *                      done = 1 when finished; any pointer may be NULL
+ *                      the overlap changes any result.  A job whose FP64
+ *                      statistics come out non-finite (NaN or Inf in its
+ *                      data) fails alone: it is marked finished with that
+ *                      error and the call goes on with the other jobs.
+ *   tvs_job_status     step 1 or 2 (3 when finished, -1 when failed), sweeps
+ *                      done in it, done = 1 when finished or failed; any
+ *                      pointer may be NULL
  *   tvs_job_result     copy d (N2 x N1) and tau (2 x (N2+1) x (N1+1)) into
  *                      the caller's device buffers (either may be NULL) on
  *                      `stream`, and the two steps' statistics into
  *                      stats[2] (may be NULL); TVS_EBUSY before the job has
- *                      finished
+ *                      finished, the job's error (TVS_ENONFINITE) if it failed
  *   tvs_job_bytes      device bytes held by the job (0 for NULL)
  *   tvs_job_destroy    wait for the device, free the job (NULL is a no-op)
  * The calls on one job must not overlap; jobs of one context share its kernel

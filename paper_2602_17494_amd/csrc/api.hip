@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "../../include/tvs.h"
@@ -849,7 +850,9 @@ struct tvs_job {
   tvs_params prm{};
   tvs_layout lay{};
   tvs_iters its{};
-  int step = 1;  // 1, 2, or 3 when finished
+  int step = 1;  // 1, 2, or 3 when finished (or failed)
+  int failed = 0;     // the error code that ended the job, 0 if none
+  std::string error;  // its message
   tvs_stats st[2]{};
   std::unique_ptr<tvs::JobState<float>> f;
   std::unique_ptr<tvs::JobState<double>> d;
@@ -1430,11 +1433,20 @@ int tvs_batch_sweep(tvs_ctx* ctx, tvs_job* const* jobs, int n, void* stream) {
       if (!jobs[i] || jobs[i]->ctx != ctx) throw Error(TVS_EINVAL, "job missing or of another context");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // a job whose FP64 statistics come out non-finite fails alone: it is
+    // marked finished with its error and the other jobs go on
     auto sweep_on = [&](tvs_job* j, hipStream_t st) {
-      if (j->dtype == TVS_F32)
-        job_sweep<float>(ctx, j, st);
-      else
-        job_sweep<double>(ctx, j, st);
+      try {
+        if (j->dtype == TVS_F32)
+          job_sweep<float>(ctx, j, st);
+        else
+          job_sweep<double>(ctx, j, st);
+      } catch (const Error& e) {
+        if (e.code != TVS_ENONFINITE) throw;
+        j->failed = e.code;
+        j->error = e.what();
+        j->step = 3;
+      }
     };
     if (n == 0) return;
     // The jobs share no device data, so their sweeps may run concurrently:
@@ -1466,11 +1478,11 @@ int tvs_job_status(const tvs_job* job, int* step, int* sweeps_done, int* done) {
     if (!job) throw Error(TVS_EINVAL, "NULL job");
     int sw = 0;
     if (job->dtype == TVS_F32) {
-      sw = job->step == 1 ? job->f->r1->done : job->f->r2->done;
+      sw = (job->step == 1 || !job->f->r2) ? job->f->r1->done : job->f->r2->done;
     } else {
-      sw = job->step == 1 ? job->d->r1->done : job->d->r2->done;
+      sw = (job->step == 1 || !job->d->r2) ? job->d->r1->done : job->d->r2->done;
     }
-    if (step) *step = job->step;
+    if (step) *step = job->failed ? -1 : job->step;
     if (sweeps_done) *sweeps_done = sw;
     if (done) *done = job->step == 3 ? 1 : 0;
   });
@@ -1480,6 +1492,7 @@ int tvs_job_result(tvs_ctx* ctx, tvs_job* job, void* d_out, void* tau_out, tvs_s
                    void* stream) {
   return guarded([&] {
     if (!ctx || !job || job->ctx != ctx) throw Error(TVS_EINVAL, "bad job");
+    if (job->failed) throw Error(job->failed, job->error);
     if (job->step != 3) throw Error(TVS_EBUSY, "the job has not finished");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1503,6 +1516,7 @@ int tvs_job_export_state(tvs_ctx* ctx, tvs_job* job, void* buf, size_t cap, size
   return guarded([&] {
     if (!ctx || !job || job->ctx != ctx) throw Error(TVS_EINVAL, "bad job");
     if (!bytes) throw Error(TVS_EINVAL, "bytes is NULL");
+    if (job->failed) throw Error(TVS_EINVAL, "the job has failed: " + job->error);
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto* b = static_cast<unsigned char*>(buf);

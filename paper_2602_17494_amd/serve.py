@@ -7,7 +7,9 @@ device footprints stays within a byte budget, advances every live job by one
 sweep per round (one tvs_batch_sweep call), and retires the jobs that have
 finished, so that requests arriving while others run join the next round and
 their work interleaves on the device with the running ones.  A job computes
-exactly what a one-shot tvs_schwarz_solve of its image computes.
+exactly what a one-shot tvs_schwarz_solve of its image computes.  A request
+whose job fails (non-finite data) is retired with its error and does not
+disturb the others; queued or running requests can be cancelled.
 """
 import time
 from dataclasses import dataclass, field
@@ -15,7 +17,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from .tvs import Context, Job, job_footprint
+from .tvs import Context, Job, TvsError, job_footprint
 
 
 @dataclass
@@ -32,12 +34,13 @@ class Request:
 @dataclass
 class Result:
     rid: int
-    d: torch.Tensor
-    tau: torch.Tensor
+    d: torch.Tensor           # None if the job failed
+    tau: torch.Tensor         # None if the job failed
     stats: list
     arrival: float
     admitted: float
     finished: float
+    error: str = ""           # the library's message if the job failed
 
     @property
     def latency(self):
@@ -80,15 +83,38 @@ class Server:
         out, keep = [], []
         for req, job, adm in self.live:
             if job.done:
-                d, tau, st = job.result()
-                self.ctx.synchronize()
-                out.append(Result(req.rid, d, tau, st, req.arrival, adm, now_fn()))
+                if job.failed:
+                    try:
+                        job.result()
+                        err = "failed"
+                    except TvsError as e:
+                        err = str(e)
+                    out.append(Result(req.rid, None, None, [], req.arrival, adm, now_fn(), err))
+                else:
+                    d, tau, st = job.result()
+                    self.ctx.synchronize()
+                    out.append(Result(req.rid, d, tau, st, req.arrival, adm, now_fn()))
                 job.close()
                 self.in_use -= req.footprint
             else:
                 keep.append((req, job, adm))
         self.live = keep
         return out
+
+    def cancel(self, rid):
+        """Drop request `rid`, queued or running (its job is freed); False if
+        it is unknown or already finished."""
+        for i, req in enumerate(self.queue):
+            if req.rid == rid:
+                del self.queue[i]
+                return True
+        for i, (req, job, _) in enumerate(self.live):
+            if req.rid == rid:
+                job.close()
+                self.in_use -= req.footprint
+                del self.live[i]
+                return True
+        return False
 
 
 def serve(ctx, requests, budget, clock=time.perf_counter, progress=None, every=50):

@@ -355,7 +355,8 @@ class Job:
         self.ctx, self._h, self.shape, self.dtype = ctx, handle, (n2, n1), dtype
 
     def status(self):
-        """(step, sweeps done in it, finished)"""
+        """(step, sweeps done in it, finished); step is -1 for a job that
+        failed (non-finite statistics), which also counts as finished."""
         st, sw, dn = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(load().tvs_job_status(self._h, ctypes.byref(st), ctypes.byref(sw), ctypes.byref(dn)))
         return st.value, sw.value, bool(dn.value)
@@ -364,12 +365,16 @@ class Job:
     def done(self):
         return self.status()[2]
 
+    @property
+    def failed(self):
+        return self.status()[0] == -1
+
     def bytes(self):
         return int(load().tvs_job_bytes(self._h))
 
     def result(self, d_out=None, tau_out=None):
         """(d, tau, [stats step 1, stats step 2]); raises TvsError (TVS_EBUSY)
-        before the job has finished."""
+        before the job has finished, and the job's error if it failed."""
         n2, n1 = self.shape
         dev = self.ctx.device
         if d_out is None:

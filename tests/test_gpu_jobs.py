@@ -180,3 +180,34 @@ def test_graph_replays_match_eager_sweeps(ctx):
         torch.cuda.synchronize()
         assert torch.equal(d, d_ref) and torch.equal(tau, tau_ref)
         job.close()
+
+
+def test_nonfinite_job_fails_alone(ctx):
+    """A job whose image holds a NaN fails at the end of Step 1 with
+    TVS_ENONFINITE; the batch call goes on, and the healthy job in the same
+    batch still equals its one-shot solve bit for bit."""
+    from paper_2602_17494_amd import TvsError, make_iters, make_layout, make_params
+    n2, n1 = 40, 56
+    _, d64 = synth.noisy_f32(n2, n1, 0.1, 13)
+    good = torch.tensor(d64, dtype=torch.float32, device=DEV)
+    bad = good.clone()
+    bad[7, 9] = float("nan")
+    prm, L, its = make_params(0.15, 10.0), make_layout(2, 2, 4, 4), make_iters(2, 3)
+    d_ref, tau_ref, _ = one_shot(ctx, good, prm, L, its)
+    jb, jg = ctx.job(bad, prm, L, its), ctx.job(good, prm, L, its)
+    rounds = 0
+    while not (jb.done and jg.done):
+        ctx.batch_sweep([j for j in (jb, jg) if not j.done])
+        rounds += 1
+    torch.cuda.synchronize()
+    assert jb.failed and jb.status()[0] == -1 and not jg.failed
+    with pytest.raises(TvsError) as e:
+        jb.result()
+    assert e.value.code == -4  # TVS_ENONFINITE
+    with pytest.raises(TvsError):
+        jb.export_state()
+    d, tau, _ = jg.result()
+    torch.cuda.synchronize()
+    assert torch.equal(d, d_ref) and torch.equal(tau, tau_ref)
+    jb.close()
+    jg.close()

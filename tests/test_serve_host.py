@@ -9,15 +9,23 @@ torch = pytest.importorskip("torch")
 
 
 class FakeJob:
-    def __init__(self, sweeps):
+    def __init__(self, sweeps, fail=False):
         self.left = sweeps
         self.closed = False
+        self.fail = fail
 
     @property
     def done(self):
         return self.left == 0
 
+    @property
+    def failed(self):
+        return self.fail and self.left == 0
+
     def result(self):
+        if self.failed:
+            from paper_2602_17494_amd import TvsError
+            raise TvsError(-4, "step 1: non-finite energy or gap")
         return torch.zeros(1), torch.zeros(1), [{}, {}]
 
     def close(self):
@@ -27,11 +35,12 @@ class FakeJob:
 class FakeCtx:
     device = "cpu"
 
-    def __init__(self, sweeps):
+    def __init__(self, sweeps, fail_ids=()):
         self.sweeps, self.created, self.batches = sweeps, [], []
+        self.fail_ids = set(fail_ids)
 
     def job(self, d0, params, layout, iters):
-        j = FakeJob(self.sweeps)
+        j = FakeJob(self.sweeps, fail=len(self.created) in self.fail_ids)
         self.created.append(j)
         return j
 
@@ -92,3 +101,34 @@ def test_serve_reports_progress_and_latencies():
     assert all(b // 2 > a // 2 for a, b in zip([0] + seen, seen))
     assert all(r.finished >= r.admitted >= r.arrival - 1e-9 for r in results)
     assert max(ctx.batches) > 1      # requests arriving together share batch calls
+
+
+def test_failed_job_is_retired_alone():
+    """A job that fails (the library reports non-finite statistics) ends as a
+    result carrying the error; the others finish normally."""
+    from paper_2602_17494_amd.serve import serve
+    ctx = FakeCtx(sweeps=2, fail_ids={1})
+    results, srv = serve(ctx, make_requests([64] * 3, [0.0] * 3), budget=1 << 40)
+    by = {r.rid: r for r in results}
+    assert by[1].d is None and "non-finite" in by[1].error
+    assert by[0].error == "" and by[2].error == "" and by[0].d is not None
+    assert srv.in_use == 0 and all(j.closed for j in ctx.created)
+
+
+def test_cancel_queued_and_running():
+    from paper_2602_17494_amd import job_footprint, make_iters, make_layout
+    from paper_2602_17494_amd.serve import Server
+    fp = job_footprint((64, 64), torch.float32, make_layout(2, 2, 8, 8), make_iters(3, 5))
+    ctx = FakeCtx(sweeps=3)
+    srv = Server(ctx, budget=2 * fp)
+    for r in make_requests([64] * 4, [0.0] * 4):
+        srv.submit(r)
+    srv.round(lambda: 0.0)                    # admits 0 and 1, sweeps them once
+    assert [r.rid for r, _, _ in srv.live] == [0, 1]
+    assert srv.cancel(1) and srv.in_use == fp and ctx.created[1].closed
+    assert srv.cancel(3) and [r.rid for r in srv.queue] == [2]
+    assert not srv.cancel(3) and not srv.cancel(99)
+    done = []
+    while srv.queue or srv.live:
+        done += [r.rid for r in srv.round(lambda: 0.0)]
+    assert sorted(done) == [0, 2]
