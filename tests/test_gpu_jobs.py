@@ -211,3 +211,20 @@ def test_nonfinite_job_fails_alone(ctx):
     assert torch.equal(d, d_ref) and torch.equal(tau, tau_ref)
     jb.close()
     jg.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_solves_are_deterministic(ctx, dtype):
+    """The same solve twice, and once more in a fresh context, gives the same
+    bits: every reduction has a fixed order and no kernel races."""
+    from paper_2602_17494_amd import Context, make_iters, make_layout, make_params
+    _, d64 = synth.noisy_f32(70, 90, 0.1, 14)
+    d0 = torch.tensor(d64, dtype=dtype, device=DEV)
+    prm, L, its = make_params(0.15, 10.0), make_layout(3, 3, 4, 6), make_iters(2, 4)
+    a = one_shot(ctx, d0, prm, L, its)
+    b = one_shot(ctx, d0, prm, L, its)
+    with Context(0) as c2:
+        c = one_shot(c2, d0, prm, L, its)
+    for x in (b, c):
+        assert torch.equal(a[0], x[0]) and torch.equal(a[1], x[1])
+        assert a[2][0]["energy"] == x[2][0]["energy"] and a[2][1]["gap"] == x[2][1]["gap"]
