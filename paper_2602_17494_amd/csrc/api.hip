@@ -1465,11 +1465,24 @@ int tvs_batch_sweep(tvs_ctx* ctx, tvs_job* const* jobs, int n, void* stream) {
     }
     TVS_HIP(hipEventRecord(ctx->bfork, s));
     for (int k = 0; k < K; ++k) TVS_HIP(hipStreamWaitEvent(ctx->bstream[k], ctx->bfork, 0));
-    for (int i = 0; i < n; ++i) sweep_on(jobs[i], ctx->bstream[i % K]);
-    for (int k = 0; k < K; ++k) {
-      TVS_HIP(hipEventRecord(ctx->bjoin[k], ctx->bstream[k]));
-      TVS_HIP(hipStreamWaitEvent(s, ctx->bjoin[k], 0));
+    auto join = [&] {
+      for (int k = 0; k < K; ++k) {
+        TVS_HIP(hipEventRecord(ctx->bjoin[k], ctx->bstream[k]));
+        TVS_HIP(hipStreamWaitEvent(s, ctx->bjoin[k], 0));
+      }
+    };
+    try {
+      for (int i = 0; i < n; ++i) sweep_on(jobs[i], ctx->bstream[i % K]);
+    } catch (...) {
+      // whatever was enqueued before the failure stays ordered before the
+      // caller's later work
+      try {
+        join();
+      } catch (...) {
+      }
+      throw;
     }
+    join();
   });
 }
 
