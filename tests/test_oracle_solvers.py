@@ -147,3 +147,82 @@ def test_irv1_xi_is_in_unit_ball():
     assert np.sqrt(xi[0] ** 2 + xi[1] ** 2).max() < 1.0
     # xi is parallel to (tau_2, -tau_1)
     assert np.abs(xi[0] * (-tau[0, :6, :7]) - xi[1] * tau[1, :6, :7]).max() < 1e-14
+
+
+# --- orientation of tau_0 and the IRV1 maps ---------------------------------
+
+def test_tau0_of_a_ramp():
+    # d = a x + b y (x = column j, y = row i): the Neumann backward differences
+    # are a and b inside their interior ranges, so tau_0 = (-D_y d, D_x d) is
+    # (-b, a) there (text after eq. ir2dualdis); a swapped or sign-flipped
+    # component gives another constant.
+    a, b = 2.0, 5.0
+    i, j = np.mgrid[0:6, 0:7]
+    t0 = sv.tau0(a * j + b * i)
+    assert np.all(t0[0, 1:6, 0:7] == -b)
+    assert np.all(t0[1, 0:6, 1:7] == a)
+
+
+def test_potential_of_tau0_recovers_the_image():
+    # (D^-_x, D^-_y) g = (R tau)^perp = (tau_2, -tau_1); for tau = tau_0 =
+    # (-D_y d, D_x d) the right side is the gradient of d, so g is d up to its
+    # first column: g = d - d[:, :1] on Omega (eq. def:backdiffNeumann and the
+    # definition of g after eq. ir2dualdis).  A flipped tau_0 gives -(d - d0).
+    # (The y-equation does not hold for tau_0 itself: D^{neum-}_x is 0 in the
+    # first column, so tau_0 is not divergence-free on the boundary ring.)
+    rng = np.random.default_rng(21)
+    d = rng.standard_normal((9, 12))
+    g = sv.irv2_potential(sv.tau0(d), 9, 12)
+    assert np.abs(g - (d - d[:, :1])).max() < 1e-13
+
+
+def test_xi_of_hand_built_fields():
+    # eq. eq:defXi2:discrete: xi = tau^perp / sqrt(|tau^perp|^2 + eps) with
+    # tau^perp = R_Omega (tau_2, -tau_1).  With |tau| = 1 and eps = 3 the root
+    # is exactly 2; eps outside the root, or a swapped or flipped component,
+    # gives other values.
+    tau = np.zeros((2, 4, 5))
+    tau[0, :, :] = 1.0          # tau = (1, 0): tau^perp = (0, -1)
+    tau[0, 1, 2], tau[1, 1, 2] = 0.0, 1.0   # tau = (0, 1): tau^perp = (1, 0)
+    xi = sv.irv1_xi(tau, 3, 4, 3.0)
+    assert xi.shape == (2, 3, 4)
+    want = np.zeros((2, 3, 4))
+    want[1] = -0.5
+    want[0, 1, 2], want[1, 1, 2] = 0.5, 0.0
+    assert np.array_equal(xi, want)
+
+
+@pytest.mark.parametrize("a,b,eps", [(0.3, -1.2, 1e-3), (-2.0, 0.5, 0.25)])
+def test_xi_of_constant_field(a, b, eps):
+    tau = np.stack([np.full((6, 7), a), np.full((6, 7), b)])
+    xi = sv.irv1_xi(tau, 5, 6, eps)
+    r = np.sqrt(a * a + b * b + eps)
+    assert np.abs(xi[0] - b / r).max() < 1e-15
+    assert np.abs(xi[1] + a / r).max() < 1e-15
+
+
+def _div_xi_bruteforce(xi):
+    # div by the explicit matrix of tests/bruteforce.py (div = -grad^T)
+    _, n2, n1 = xi.shape
+    dmat = bf.divergence_matrix(n2, n1)
+    return (dmat @ np.concatenate([xi[0].ravel(), xi[1].ravel()])).reshape(n2, n1)
+
+
+@pytest.mark.parametrize("seed,alpha,eps", [(31, 10.0, 1e-3), (32, 3.0, 0.5)])
+def test_irv1_matches_bruteforce_4x4(seed, alpha, eps):
+    # IRV1 (eq. ir1dualdis with eq. eq:tau_hat) solves the ROF problem of
+    # eq. IRPXi_ROF, whose data is d0 - div xi / alpha.  The SLSQP solver of
+    # that ROF dual, fed the data built here with its own xi and div, must
+    # give the same image as the oracle's chain xi -> data -> Chambolle ->
+    # image.
+    rng = np.random.default_rng(seed)
+    d0 = rng.uniform(0, 1, (4, 4))
+    tau = rng.standard_normal((2, 5, 5))
+    tp1, tp2 = tau[1, :4, :4], -tau[0, :4, :4]
+    root = np.sqrt(tp1 ** 2 + tp2 ** 2 + eps)
+    xi_ref = np.stack([tp1 / root, tp2 / root])
+    u_bf, _ = bf.rof_bruteforce(d0 - _div_xi_bruteforce(xi_ref) / alpha, alpha)
+    xi = sv.irv1_xi(tau, 4, 4, eps)
+    p = sv.chambolle_rof(sv.irv1_data(d0, xi, alpha), 20000)
+    d = sv.irv1_image(d0, p, xi, alpha)
+    assert np.abs(d - u_bf).max() < 1e-8
