@@ -22,7 +22,10 @@
  *     the subdomain, eqs. locglobprojpart1 and locglobprojpart3).
  *
  * Grids, layout and ownership
- *   The image grid Omega has N2 rows (y) and N1 columns (x), N2, N1 >= 2.
+ *   The image grid Omega has N2 rows (y) and N1 columns (x), 2 <= N2, N1 <=
+ *   5119 and (N2+1)(N1+1) <= 2^28: the inverse Laplacian of Omega-tilde runs
+ *   as FFTs of smooth lengths >= 2(N+1) - 1 held in one workgroup's LDS
+ *   (at most 10240 points per axis); larger shapes give TVS_EINVAL.
  *   The Step-1 grid Omega-tilde has (N2+1) x (N1+1) points and holds Omega as
  *   its first N2 rows and N1 columns (Section 4.1).  Arrays are row-major:
  *     image  d0, d      : N2 * N1 values
@@ -155,7 +158,7 @@ int tvs_schwarz_solve(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dt
 
 /* The orthogonal projection onto divergence-free fields of an n2 x n1 grid,
  * P u = u - grad (Delta)^dagger div u (eq. formula:PKh, Proposition
- * prop:DisProj), n2, n1 >= 3: u_in and u_out are 2 planes of n2*n1 (x- then
+ * prop:DisProj), 3 <= n2, n1 <= 5120: u_in and u_out are 2 planes of n2*n1 (x- then
  * y-component); they may alias.  Step 1 applies this operator on
  * Omega-tilde. */
 int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dtype dtype,
@@ -193,8 +196,11 @@ int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* lau
  * interleave the sweeps of many jobs, admit new ones between sweeps and
  * retire finished ones (continuous batching).
  *   tvs_job_footprint  bytes of device memory a job of this shape needs (its
- *                      own state, plus the Green-function table the context
- *                      keeps once per grid size), computed on the host
+ *                      own state, plus the Green-function table of its grid,
+ *                      which tvs_job_create builds and frees again unless the
+ *                      context already holds one from a one-shot call), computed
+ *                      on the host; TVS_EINVAL for shapes tvs_job_create
+ *                      would refuse
  *   tvs_job_create     validate as tvs_schwarz_solve, allocate and build the
  *                      job's state, copy d0 (device pointer, N2 x N1; the
  *                      caller may reuse it on return) and run the Step-1

@@ -293,10 +293,25 @@ Partials partials(tvs_ctx* c) {
   return Partials{c->partials.as<double>(), 1024};
 }
 
-void check_params(const tvs_params* prm, int N2, int N1) {
-  if (!prm) throw Error(TVS_EINVAL, "params is NULL");
+// the inverse Laplacian of a grid of n2 x n1 points (Step 1 runs it on
+// Omega-tilde, (N2+1) x (N1+1)) needs transforms of about twice each side
+void check_grid_sides(int n2, int n1) {
+  if (!green_side_ok(n2) || !green_side_ok(n1))
+    throw Error(TVS_EINVAL, "grid of " + std::to_string(n2) + " x " + std::to_string(n1) +
+                                " points: sides above " + std::to_string(kGreenMaxSide) +
+                                " points are not supported (the transforms of the inverse Laplacian "
+                                "would exceed the LDS)");
+}
+
+void check_shape(int N2, int N1) {
   if (N2 < 2 || N1 < 2) throw Error(TVS_EINVAL, "image must be at least 2 x 2");
   if ((long long)(N2 + 1) * (N1 + 1) > (1LL << 28)) throw Error(TVS_EINVAL, "image too large");
+  check_grid_sides(N2 + 1, N1 + 1);
+}
+
+void check_params(const tvs_params* prm, int N2, int N1) {
+  if (!prm) throw Error(TVS_EINVAL, "params is NULL");
+  check_shape(N2, N1);
   if (!(prm->delta > 0) || !(prm->alpha > 0)) throw Error(TVS_EINVAL, "delta and alpha must be > 0");
   if (!(prm->t > 0) || prm->t > 0.125) throw Error(TVS_EINVAL, "t must lie in (0, 1/8]");
   if (!(prm->h > 0)) throw Error(TVS_EINVAL, "h must be > 0");
@@ -316,9 +331,12 @@ double alpha_hat_of(const tvs_layout* l) {
   return l->alpha_hat;
 }
 
+// cache_table = false (jobs): the grid's Green-function table is only needed
+// while the plans are built; use the context's if it has one, else build a
+// transient one, so that jobs of many grid sizes do not grow the context
 template <typename T>
 std::unique_ptr<Step1Problem<T>> make_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l,
-                                            hipStream_t s, int lp_kind = TVS_LP_IMAGE) {
+                                            hipStream_t s, int lp_kind = TVS_LP_IMAGE, bool cache_table = true) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
   auto P = std::make_unique<Step1Problem<T>>();
   const int n2 = N2 + 1, n1 = N1 + 1;
@@ -327,7 +345,20 @@ std::unique_ptr<Step1Problem<T>> make_step1(tvs_ctx* c, int N2, int N1, double h
   P->ss.ax = make_axis(n1, l->M1, l->s_x, "M1");
   build_subs1(P->ss, n2, n1, s);
   P->plain = (l->M2 == 1 && l->M1 == 1);
-  GreenTable& tab = get_table(c, n2, n1, h, s);
+  std::unique_ptr<GreenTable> own;
+  const GreenTable* tp = nullptr;
+  if (cache_table) {
+    tp = &get_table(c, n2, n1, h, s);
+  } else {
+    auto it = c->tables.find(GridKey{n2, n1, h});
+    if (it != c->tables.end()) {
+      tp = it->second.get();
+    } else {
+      own = std::make_unique<GreenTable>(n2, n1, h, s);
+      tp = own.get();
+    }
+  }
+  const GreenTable& tab = *tp;
   P->global = std::make_unique<GreenPlan<T>>(tab, std::vector<std::array<int, 4>>{{0, 0, n2, n1}}, s);
   if (!P->plain) {
     std::vector<std::array<int, 4>> boxes;
@@ -881,7 +912,7 @@ void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s,
   st->part.alloc(sizeof(double) * 1024);
   st->e1.alloc(sizeof(double) * (size_t(j->its.sweeps) + 3));
   st->e2.alloc(sizeof(double) * (size_t(j->its.sweeps) + 3));
-  st->p1 = make_step1<T>(c, N2, N1, j->prm.h, &j->lay, s);
+  st->p1 = make_step1<T>(c, N2, N1, j->prm.h, &j->lay, s, TVS_LP_IMAGE, false);
   st->p2 = make_step2<T>(N2, N1, j->prm.h, &j->lay, s);
   TVS_HIP(hipMemcpyAsync(st->d0.p, d0, esz * size_t(N2) * N1, kind, s));
   st->r1 = std::make_unique<Step1Run<T>>(*st->p1, st->d0.template as<T>(), N2, N1, &j->prm, &j->lay, &j->its,
@@ -1300,6 +1331,8 @@ int tvs_project_div_free(tvs_ctx* ctx, const void* u_in, int n2, int n1, tvs_dty
   return guarded([&] {
     if (!ctx || !u_in || !u_out) throw Error(TVS_EINVAL, "NULL argument");
     if (n2 < 2 || n1 < 2) throw Error(TVS_EINVAL, "grid must be at least 2 x 2");
+    if ((long long)n2 * n1 > (1LL << 28)) throw Error(TVS_EINVAL, "grid too large");
+    check_grid_sides(n2, n1);
     if (!(h > 0)) throw Error(TVS_EINVAL, "h must be > 0");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1384,7 +1417,7 @@ int tvs_job_footprint(int N2, int N1, tvs_dtype dtype, const tvs_layout* layout,
                       size_t* bytes) {
   return guarded([&] {
     if (!layout || !iters || !bytes) throw Error(TVS_EINVAL, "NULL argument");
-    if (N2 < 2 || N1 < 2) throw Error(TVS_EINVAL, "image must be at least 2 x 2");
+    check_shape(N2, N1);
     check_iters(iters);
     // the job's own state plus the Green-function table of its grid, which the
     // context holds once per grid size

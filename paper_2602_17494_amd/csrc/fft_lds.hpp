@@ -262,6 +262,121 @@ __device__ __forceinline__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* bbuf, const Fft
 }
 
 // ---------------------------------------------------------------------------
+// One-buffer variant for transforms too long for two LDS buffers.  Every
+// pass loads the inputs of all its butterflies into registers, waits at a
+// barrier, and writes the outputs back into the same buffer, so the whole
+// LDS (160 KB per workgroup on gfx950) holds one copy of the data: up to
+// kLdsElems<T> elements (10240 complex float64, 20480 complex float32) per
+// workgroup, with 1024 threads.  The caller guarantees batch * n <=
+// kLdsElems<T>, which bounds the butterflies a thread holds per pass.
+// ---------------------------------------------------------------------------
+constexpr int kLdsBytes = 160 * 1024;
+template <typename T> constexpr int kLdsElems = kLdsBytes / int(sizeof(cplx<T>));
+// largest radix the one-buffer plans use (make_fft_desc's max_radix)
+template <typename T> constexpr int kLongRadix = sizeof(T) == 8 ? 4 : 8;
+
+template <typename T, int NT, int R, typename LD, typename ST>
+__device__ __forceinline__ void fft_pass_1b(LD& ld, ST& st, int batch, FastDiv fls, FastDiv fnbf,
+                                            int twstep, const cplx<T>* __restrict__ tw, bool inv) {
+  using C = cplx<T>;
+  constexpr int MB = (kLdsElems<T> + R * NT - 1) / (R * NT);  // butterflies per thread
+  const int nbf = fnbf.d, Ls = fls.d;
+  const int total = nbf * batch;
+  C v[MB][R];
+  int bb[MB], base[MB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int jj = threadIdx.x + m * NT;
+    if (jj < total) {
+      const int b = fnbf.div(jj);
+      const int j = jj - b * nbf;
+      const int g = fls.div(j);
+      const int k = j - g * Ls;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[m][t] = ld(b, j + t * nbf, t);
+      if (Ls > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          C w = tw[k * t * twstep];
+          if (inv) w.y = -w.y;
+          v[m][t] = cmul(v[m][t], w);
+        }
+      }
+      bb[m] = b;
+      base[m] = g * Ls * R + k;
+    }
+  }
+  __syncthreads();  // every input of the pass is read before any output lands
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int jj = threadIdx.x + m * NT;
+    if (jj < total) {
+      butterfly<R, T>(v[m], inv);
+#pragma unroll
+      for (int t = 0; t < R; ++t) st(bb[m], base[m] + t * Ls, v[m][t]);
+    }
+  }
+}
+
+template <typename T, int NT, typename LD, typename ST>
+__device__ __forceinline__ void fft_pass_radix_1b(int radix, LD& ld, ST& st, int batch, FastDiv fls,
+                                                  FastDiv fnbf, int twstep, const cplx<T>* __restrict__ tw,
+                                                  bool inv) {
+  // only the radices of make_fft_desc(n, kLongRadix<T>) are instantiated,
+  // so that the register budget is that of the largest of them
+  switch (radix) {
+    case 8:
+      if constexpr (kLongRadix<T> >= 8) fft_pass_1b<T, NT, 8>(ld, st, batch, fls, fnbf, twstep, tw, inv);
+      break;
+    case 4: fft_pass_1b<T, NT, 4>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    case 2: fft_pass_1b<T, NT, 2>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    case 3: fft_pass_1b<T, NT, 3>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+    default: fft_pass_1b<T, NT, 5>(ld, st, batch, fls, fnbf, twstep, tw, inv); break;
+  }
+}
+
+// All passes of d in one LDS buffer: pass 0 reads through `first` and writes
+// buf; the middle passes transform buf in place; the last pass writes
+// through `last`.  A barrier separates consecutive passes.  What `first`
+// reads from LDS must be complete (barrier) before the call.
+template <typename T, int NT, typename LD, typename ST>
+__device__ __forceinline__ void fft_run_1b(const FftDesc& d, LD& first, ST& last, cplx<T>* buf, int stride,
+                                           int batch, const cplx<T>* __restrict__ tw, bool inv) {
+  LdsSeq<T> io{buf, stride};
+  const int np = d.npass;
+  for (int p = 0; p < np; ++p) {
+    if (p == 0 && np == 1) {
+      fft_pass_radix_1b<T, NT>(d.radix[0], first, last, batch, d.ls[0], d.nbf[0], d.twstep[0], tw, inv);
+    } else if (p == 0) {
+      fft_pass_radix_1b<T, NT>(d.radix[0], first, io, batch, d.ls[0], d.nbf[0], d.twstep[0], tw, inv);
+    } else if (p < np - 1) {
+      fft_pass_radix_1b<T, NT>(d.radix[p], io, io, batch, d.ls[p], d.nbf[p], d.twstep[p], tw, inv);
+    } else {
+      fft_pass_radix_1b<T, NT>(d.radix[p], io, last, batch, d.ls[p], d.nbf[p], d.twstep[p], tw, inv);
+    }
+    if (p < np - 1) __syncthreads();
+  }
+}
+
+// As fft_run_1b with the result left in buf; ends with a barrier.
+template <typename T, int NT, typename LD>
+__device__ __forceinline__ cplx<T>* fft_run_to_lds_1b(const FftDesc& d, LD& first, cplx<T>* buf, int stride,
+                                                      int batch, const cplx<T>* __restrict__ tw, bool inv) {
+  LdsSeq<T> o{buf, stride};
+  fft_run_1b<T, NT>(d, first, o, buf, stride, batch, tw, inv);
+  __syncthreads();
+  return buf;
+}
+
+// Transform `batch` sequences held in buf in place; ends with a barrier.
+template <typename T, int NT>
+__device__ __forceinline__ cplx<T>* fft_lds_1b(cplx<T>* buf, const FftDesc& d, int stride, int batch,
+                                               const cplx<T>* __restrict__ tw, bool inv) {
+  LdsSeq<T> in{buf, stride};
+  return fft_run_to_lds_1b<T, NT>(d, in, buf, stride, batch, tw, inv);
+}
+
+// ---------------------------------------------------------------------------
 // The same passes for a transform length fixed at compile time: with the
 // radix, butterfly count, Ls and twiddle step of every pass known, the
 // butterfly and twiddle index arithmetic folds into shifts, masks and

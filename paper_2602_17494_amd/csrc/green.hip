@@ -25,6 +25,10 @@ int smooth_even_at_least(int n) {
   return m;
 }
 
+int green_length(int side) { return smooth_even_at_least(2 * side - 1); }
+
+bool green_side_ok(int side) { return side >= 1 && lds_round(green_length(side)) <= kLdsElems<double>; }
+
 FastDiv make_fastdiv(int d) {
   if (d < 1 || d >= (1 << 16)) throw Error(-1, "divisor out of range");
   FastDiv f{};
@@ -33,7 +37,7 @@ FastDiv make_fastdiv(int d) {
   return f;
 }
 
-FftDesc make_fft_desc(int n) {
+FftDesc make_fft_desc(int n, int max_radix) {
   FftDesc d{};
   d.n = n;
   int m = n, k = 0;
@@ -42,10 +46,12 @@ FftDesc make_fft_desc(int n) {
     d.radix[k++] = r;
     m /= r;
   };
-  while (m % 8 == 0) push(8);
+  if (max_radix >= 8)
+    while (m % 8 == 0) push(8);
   while (m % 4 == 0) push(4);
   while (m % 2 == 0) push(2);
-  while (m % 9 == 0) push(9);
+  if (max_radix >= 9)
+    while (m % 9 == 0) push(9);
   while (m % 3 == 0) push(3);
   while (m % 5 == 0) push(5);
   if (m != 1) throw Error(-1, "FFT length " + std::to_string(n) + " is not 2^a 3^b 5^c");
@@ -193,7 +199,7 @@ __device__ __forceinline__ double g_lookup(const double* __restrict__ g, int n2,
 // bj + d(m_j)), d(m) = m below ceil(L/2) and m - L above (the offsets a
 // linear convolution of a box with itself needs).  Output row-major
 // [slot][m_i][k_j].
-template <int NT>
+template <int NT, bool OB>
 __global__ __launch_bounds__(NT) void k_spec_rows(const double* __restrict__ g, int n2, int n1,
                                                   const int4* __restrict__ keys, int Li, int Lj,
                                                   FftDesc fj, const cplx<double>* __restrict__ twj,
@@ -215,7 +221,8 @@ __global__ __launch_bounds__(NT) void k_spec_rows(const double* __restrict__ g, 
     buf[lds_swz(qq * Lj + c)] = cplx<double>{va, vb};
   }
   __syncthreads();
-  const cplx<double>* res = fft_lds<double, NT>(buf, buf + lds_round(ppw * Lj), fj, Lj, ppw, twj, false);
+  const cplx<double>* res = OB ? fft_lds_1b<double, NT>(buf, fj, Lj, ppw, twj, false)
+                               : fft_lds<double, NT>(buf, buf + lds_round(ppw * Lj), fj, Lj, ppw, twj, false);
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int qq = e / Lh, k = e - qq * Lh;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_spec_rows(const double* __restrict__ g, 
 // Forward FFT along y, then the flip phases and the 1/(Li Lj) normalisation
 // of the inverse transforms are folded in; output in T, column-major
 // [slot][k_j][k_i].
-template <typename T, int NT>
+template <typename T, int NT, bool OB>
 __global__ __launch_bounds__(NT) void k_spec_cols(const cplx<double>* __restrict__ in,
                                                   const int4* __restrict__ keys, int Li, int Lj,
                                                   FftDesc fi, const cplx<double>* __restrict__ twi,
@@ -249,7 +256,8 @@ __global__ __launch_bounds__(NT) void k_spec_cols(const cplx<double>* __restrict
     buf[lds_swz(c * Li + r)] = (k < Lh) ? in[base + static_cast<size_t>(r) * Lh + k] : cplx<double>{0.0, 0.0};
   }
   __syncthreads();
-  const cplx<double>* res = fft_lds<double, NT>(buf, buf + lds_round(cpw * Li), fi, Li, cpw, twi, false);
+  const cplx<double>* res = OB ? fft_lds_1b<double, NT>(buf, fi, Li, cpw, twi, false)
+                               : fft_lds<double, NT>(buf, buf + lds_round(cpw * Li), fi, Li, cpw, twi, false);
   const double scale = 1.0 / (double(Li) * double(Lj));
   for (int e = threadIdx.x; e < cpw * Li; e += NT) {
     const int c = e / Li, r = e - c * Li;
@@ -295,8 +303,9 @@ __device__ __forceinline__ const cplx<T>* stage_twiddles(cplx<T>* lds, const cpl
 constexpr int scol_of(int sl) { return sl == 512 ? 272 : sl == 576 ? 304 : 368; }
 
 // SL = 512, 576 or 648: the transform length is fixed at compile time
-// (FftOf<SL>), else 0.
-template <typename T, int NT, bool TWL, int SL>
+// (FftOf<SL>), else 0.  OB: one LDS buffer (long transforms, 1024 threads,
+// global twiddles).
+template <typename T, int NT, bool TWL, int SL, bool OB>
 __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
                                                        Frame uf) {
   using C = cplx<T>;
@@ -324,6 +333,8 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   const C* res;
   if constexpr (SL != 0)
     res = fft_lds_s<T, NT, FftOf<SL>>(buf, buf + lds_round(ppw * Lj), ppw, tw, false);
+  else if constexpr (OB)
+    res = fft_lds_1b<T, NT>(buf, d.fj, Lj, ppw, tw, false);
   else
     res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
   const int scol = SL ? scol_of(SL) : d.scol;
@@ -411,7 +422,7 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
 // tile of neighbouring boxes; boxes of one subdomain column then share an
 // XCD and its L2 for the window spectra they have in common.
 // (at most 128 VGPRs, so that four 256-thread workgroups fit on a CU)
-template <typename T, int NT, bool TWL, int SL>
+template <typename T, int NT, bool TWL, int SL, bool OB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_green_cols(GreenDev<T> d) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
@@ -435,7 +446,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   auto st_s = [&](int c, int r, C v) {
     if (c < ncol && r < bx.ni) S[c * scol + r] = v;
   };
-  if constexpr (sizeof(T) == 4 && SL != 0) {
+  if constexpr (OB) {
+    // one LDS buffer: forward transform in place; Phi in place, one thread
+    // per frequency pair (k, -k), which read each other's X; then the
+    // inverse transform in place
+    C* X = fft_run_to_lds_1b<T, NT>(d.fi, ld_s, bufa, Li, cpw, tw, false);
+    const int half = Li / 2 + 1;
+    for (int e = threadIdx.x; e < cpw * half; e += NT) {
+      const int c = e / half, k = e - c * half, kn = k == 0 ? 0 : Li - k;
+      const int o = c * Li + k, on = c * Li + kn;
+      C pk{T(0), T(0)}, pn{T(0), T(0)};
+      if (c < ncol) {
+        const C x = X[lds_swz(o)], xn = X[lds_swz(on)];
+        pk = combine_phi(x, xn, phi_coef(s00[o], s01[o], s10[o], s11[o]));
+        pn = combine_phi(xn, x, phi_coef(s00[on], s01[on], s10[on], s11[on]));
+      }
+      X[lds_swz(o)] = pk;
+      if (kn != k) X[lds_swz(on)] = pn;
+    }
+    __syncthreads();
+    LdsSeq<T> io{X, Li};
+    fft_run_1b<T, NT>(d.fi, io, st_s, X, Li, cpw, tw, true);
+    return;
+  } else if constexpr (sizeof(T) == 4 && SL != 0) {
     // One butterfly per thread in the first inverse pass (the plan selects
     // this variant only when cpw * 72 <= NT): its window-spectrum values are
     // loaded before the forward transform, so that their latency overlaps it.
@@ -476,7 +509,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
 }
 
-template <typename T, int NT, bool TWL, int SL>
+template <typename T, int NT, bool TWL, int SL, bool OB>
 __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restrict__ phi, Frame pf) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
@@ -508,6 +541,8 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   };
   if constexpr (SL != 0)
     fft_run_s<T, NT, FftOf<SL>>(ld, st, buf, buf + lds_round(ppw * Lj), ppw, tw, true);
+  else if constexpr (OB)
+    fft_run_1b<T, NT>(d.fj, ld, st, buf, Lj, ppw, tw, true);
   else
     fft_run<T, NT>(d.fj, ld, st, buf, buf + lds_round(ppw * Lj), Lj, ppw, tw, true);
 }
@@ -528,16 +563,28 @@ static void allow_lds(F* f, size_t bytes) {
 // using 1024 threads when 256 cannot stage them, within `max_lds` bytes.
 struct Batch {
   int nt, batch;
+  bool ob;  // one LDS buffer (fft_run_1b): 1024 threads, global twiddles
 };
+// the one-buffer engine: as many sequences as the LDS holds, up to `want`
+template <typename T>
+static Batch pick_batch_1b(int n, int want) {
+  if (lds_round(n) > kLdsElems<T>)
+    throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS capacity (" +
+                        std::to_string(kLdsElems<T>) + " elements)");
+  return Batch{kFftThreadsLong, std::max(1, std::min(want, kLdsElems<T> / lds_round(n))), true};
+}
 template <typename T>
 static Batch pick_batch(int n, int want, size_t max_lds) {
   const size_t elem_bytes = sizeof(cplx<T>);
   constexpr int cs = FftCap<T, kFftThreads>::elems, cl = FftCap<T, kFftThreadsLong>::elems;
-  if (n > kFftThreadsLong * cl)
-    throw Error(-1, "FFT length " + std::to_string(n) + " exceeds the LDS engine capacity");
+  // two buffers of one sequence do not fit, or the thread count cannot cover
+  // the passes: the one-buffer engine
+  if (n > kFftThreadsLong * cl || 2 * size_t(lds_round(n)) * elem_bytes > size_t(kLdsBytes))
+    return pick_batch_1b<T>(n, want);
   const int by_lds = std::max<int>(1, int(max_lds / (2 * size_t(lds_round(n)) * elem_bytes)));
   const int target = std::max(1, std::min(want, by_lds));
   Batch b{};
+  b.ob = false;
   if (size_t(target) * n <= size_t(kFftThreads) * cs) {
     b.nt = kFftThreads;
     b.batch = target;
@@ -612,20 +659,26 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     DevBuf tmp(sizeof(cplx<double>) * std::min(chunk, nslot) * per_slot);
     const Batch br = pick_batch<double>(Lj, 8, 80 * 1024);
     const Batch bc = pick_batch<double>(Li, 8, 80 * 1024);
-    const size_t lds_r = 2 * size_t(lds_round(br.batch * Lj)) * sizeof(cplx<double>);
-    const size_t lds_c = 2 * size_t(lds_round(bc.batch * Li)) * sizeof(cplx<double>);
-    auto kr = br.nt == kFftThreads ? k_spec_rows<kFftThreads> : k_spec_rows<kFftThreadsLong>;
-    auto kc = bc.nt == kFftThreads ? k_spec_cols<T, kFftThreads> : k_spec_cols<T, kFftThreadsLong>;
+    const size_t lds_r = (br.ob ? 1 : 2) * size_t(lds_round(br.batch * Lj)) * sizeof(cplx<double>);
+    const size_t lds_c = (bc.ob ? 1 : 2) * size_t(lds_round(bc.batch * Li)) * sizeof(cplx<double>);
+    // the one-buffer engine holds all butterflies of a pass in registers:
+    // radices of at most 4 keep that within the register budget for float64
+    const FftDesc sfi = bc.ob ? make_fft_desc(Li, kLongRadix<double>) : fi;
+    const FftDesc sfj = br.ob ? make_fft_desc(Lj, kLongRadix<double>) : fj;
+    auto kr = br.ob ? k_spec_rows<kFftThreadsLong, true>
+                    : br.nt == kFftThreads ? k_spec_rows<kFftThreads, false> : k_spec_rows<kFftThreadsLong, false>;
+    auto kc = bc.ob ? k_spec_cols<T, kFftThreadsLong, true>
+                    : bc.nt == kFftThreads ? k_spec_cols<T, kFftThreads, false> : k_spec_cols<T, kFftThreadsLong, false>;
     allow_lds(kr, lds_r);
     allow_lds(kc, lds_c);
     for (size_t s0 = 0; s0 < nslot; s0 += chunk) {
       const int ns = int(std::min(chunk, nslot - s0));
       hipLaunchKernelGGL(kr, dim3((Li / 2 + br.batch - 1) / br.batch, ns), dim3(br.nt), lds_r, s,
-                         table.g.as<double>(), n2, n1, keys_d.as<int4>() + s0, Li, Lj, fj,
+                         table.g.as<double>(), n2, n1, keys_d.as<int4>() + s0, Li, Lj, sfj,
                          tw_j64.as<cplx<double>>(), tmp.as<cplx<double>>(), br.batch);
       TVS_LAUNCH_CHECK();
       hipLaunchKernelGGL(kc, dim3((Lh + bc.batch - 1) / bc.batch, ns), dim3(bc.nt), lds_c, s,
-                         tmp.as<cplx<double>>(), keys_d.as<int4>() + s0, Li, Lj, fi,
+                         tmp.as<cplx<double>>(), keys_d.as<int4>() + s0, Li, Lj, sfi,
                          tw_i64.as<cplx<double>>(), tw_j64.as<cplx<double>>(),
                          spec_.as<cplx<T>>() + s0 * per_slot, bc.batch);
       TVS_LAUNCH_CHECK();
@@ -636,8 +689,15 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   // 8 row pairs (16 rows) per workgroup give 128-byte chunks of float32 half
   // spectra in the transposed layout; the column pass, which is bound by
   // its barriers rather than by HBM, keeps 256-thread workgroups
-  const Batch br = pick_batch<T>(Lj, 8, 80 * 1024);
-  const Batch bc = pick_batch<T>(Li, std::max(1, (kFftThreads * FftCap<T, kFftThreads>::elems) / Li), 80 * 1024);
+  Batch br = pick_batch<T>(Lj, 8, 80 * 1024);
+  Batch bc = pick_batch<T>(Li, std::max(1, (kFftThreads * FftCap<T, kFftThreads>::elems) / Li), 80 * 1024);
+  // a transform too long for two LDS buffers puts all three passes on the
+  // one-buffer engine (one kernel variant for long plans)
+  ob_ = br.ob || bc.ob;
+  if (ob_) {
+    br = pick_batch_1b<T>(Lj, br.ob ? br.batch : 8);
+    bc = pick_batch_1b<T>(Li, 1);
+  }
   nt_rows_ = br.nt;
   nt_cols_ = bc.nt;
   dev_.n2 = n2;
@@ -657,10 +717,10 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   dev_.tw_j = tw_j_.as<cplx<T>>();
   dev_.S = S_.as<cplx<T>>();
   dev_.spec = spec_.as<cplx<T>>();
-  dev_.fi = fi;
-  dev_.fj = fj;
-  twl_rows_ = Lj * sizeof(cplx<T>) <= 16 * 1024;
-  twl_cols_ = Li * sizeof(cplx<T>) <= 16 * 1024;
+  dev_.fi = ob_ ? make_fft_desc(Li, kLongRadix<T>) : fi;
+  dev_.fj = ob_ ? make_fft_desc(Lj, kLongRadix<T>) : fj;
+  twl_rows_ = !ob_ && Lj * sizeof(cplx<T>) <= 16 * 1024;
+  twl_cols_ = !ob_ && Li * sizeof(cplx<T>) <= 16 * 1024;
   for_each_variant([&](auto rf, auto cf, auto ri) {
     allow_lds(rf, lds_rows());
     allow_lds(ri, lds_rows());
@@ -670,11 +730,11 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
 
 template <typename T>
 size_t GreenPlan<T>::lds_rows() const {
-  return (2 * size_t(lds_round(dev_.ppw * Lj)) + (twl_rows_ ? size_t(Lj) : 0)) * sizeof(cplx<T>);
+  return ((ob_ ? 1 : 2) * size_t(lds_round(dev_.ppw * Lj)) + (twl_rows_ ? size_t(Lj) : 0)) * sizeof(cplx<T>);
 }
 template <typename T>
 size_t GreenPlan<T>::lds_cols() const {
-  return (2 * size_t(lds_round(dev_.cpw * Li)) + (twl_cols_ ? size_t(Li) : 0)) * sizeof(cplx<T>);
+  return ((ob_ ? 1 : 2) * size_t(lds_round(dev_.cpw * Li)) + (twl_cols_ ? size_t(Li) : 0)) * sizeof(cplx<T>);
 }
 
 // Calls f(rows_fwd, cols, rows_inv) with the kernel instantiations this plan
@@ -683,10 +743,15 @@ template <typename T>
 template <typename F>
 void GreenPlan<T>::for_each_variant(F&& f) const {
   auto pick = [&](auto nt_r, auto nt_c, auto twr, auto twc, auto sl) {
-    f(k_green_rows_fwd<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value>,
-      k_green_cols<T, decltype(nt_c)::value, decltype(twc)::value, decltype(sl)::value>,
-      k_green_rows_inv<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value>);
+    f(k_green_rows_fwd<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value, false>,
+      k_green_cols<T, decltype(nt_c)::value, decltype(twc)::value, decltype(sl)::value, false>,
+      k_green_rows_inv<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value, false>);
   };
+  if (ob_) {
+    f(k_green_rows_fwd<T, kFftThreadsLong, false, 0, true>, k_green_cols<T, kFftThreadsLong, false, 0, true>,
+      k_green_rows_inv<T, kFftThreadsLong, false, 0, true>);
+    return;
+  }
   using S = std::integral_constant<int, kFftThreads>;
   using L = std::integral_constant<int, kFftThreadsLong>;
   using Y = std::true_type;

@@ -59,6 +59,13 @@ __device__ __forceinline__ T div_at(const T* __restrict__ u, const Frame& f, int
   return ((a - am) + (c - cm)) * inv_h;
 }
 
+// Transform length of a box side (smooth, >= 2 side - 1), and whether a
+// plan can hold it: the window spectra are built in float64 in one LDS
+// buffer, so L <= 10240 (box sides up to 5120) for both compute types.
+int green_length(int side);
+bool green_side_ok(int side);
+constexpr int kGreenMaxSide = 5120;
+
 // Tabulated torus kernel G(u, v), u in [0, n2], v in [0, n1], float64.
 struct GreenTable {
   int n2, n1;
@@ -109,6 +116,7 @@ class GreenPlan {
   GreenDev<T> dev_{};
   int nt_rows_ = 0, nt_cols_ = 0;
   bool twl_rows_ = false, twl_cols_ = false;  // twiddle tables staged in LDS
+  bool ob_ = false;  // transforms on the one-buffer LDS engine (long lengths)
   size_t lds_rows() const, lds_cols() const;
   template <typename F> void for_each_variant(F&& f) const;
   double sum_ni_lh_ = 0, sum_box_px_ = 0;

@@ -239,6 +239,7 @@ struct FftDesc {
 
 // smallest even integer >= n whose only prime factors are 2, 3 and 5
 int smooth_even_at_least(int n);
-FftDesc make_fft_desc(int n);
+// radices 8, 4, 2, 9, 3, 5 in that order of preference, none above max_radix
+FftDesc make_fft_desc(int n, int max_radix = 9);
 
 }  // namespace tvs

@@ -9,7 +9,9 @@ finished, so that requests arriving while others run join the next round and
 their work interleaves on the device with the running ones.  A job computes
 exactly what a one-shot tvs_schwarz_solve of its image computes.  A request
 whose job fails (non-finite data) is retired with its error and does not
-disturb the others; queued or running requests can be cancelled.
+disturb the others; so is a request the library refuses (a shape it does not
+support, a footprint over the budget), at submission or at admission.
+Queued or running requests can be cancelled.
 """
 import time
 from dataclasses import dataclass, field
@@ -56,27 +58,48 @@ class Server:
     in_use: int = 0
     peak_in_use: int = 0
     rounds: int = 0
+    max_live: int = 0                 # > 0: at most this many live jobs
+    refused: list = field(default_factory=list)  # results of refused requests, not yet returned
 
-    def submit(self, req: Request):
-        req.footprint = job_footprint(tuple(req.d0.shape), req.d0.dtype, req.layout, req.iters)
+    def _refuse(self, req, now, msg):
+        self.refused.append(Result(req.rid, None, None, [], req.arrival, now, now, msg))
+
+    def submit(self, req: Request, now=0.0):
+        """Queue a request; False (and a result carrying the reason, returned
+        by the next round) if the library refuses its shape or its footprint
+        exceeds the whole budget."""
+        try:
+            req.footprint = job_footprint(tuple(req.d0.shape), req.d0.dtype, req.layout, req.iters)
+        except TvsError as e:
+            self._refuse(req, now, str(e))
+            return False
         if req.footprint > self.budget:
-            raise ValueError(f"request {req.rid} needs {req.footprint} bytes, over the budget")
+            self._refuse(req, now, f"needs {req.footprint} bytes, over the budget of {self.budget}")
+            return False
         self.queue.append(req)
+        return True
 
     def _admit(self, now):
-        while self.queue and self.in_use + self.queue[0].footprint <= self.budget:
+        while (self.queue and self.in_use + self.queue[0].footprint <= self.budget
+               and (self.max_live <= 0 or len(self.live) < self.max_live)):
             req = self.queue.pop(0)
-            job = self.ctx.job(req.d0, req.params, req.layout, req.iters)
+            try:
+                job = self.ctx.job(req.d0, req.params, req.layout, req.iters)
+            except TvsError as e:
+                self._refuse(req, now, str(e))
+                continue
             self.in_use += req.footprint
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             self.live.append((req, job, now))
 
     def round(self, now_fn):
         """Admit what fits, advance every live job by one sweep, retire the
-        finished ones; returns their results."""
+        finished ones; returns their results (and those of requests refused
+        since the last round)."""
         self._admit(now_fn())
+        refused, self.refused = self.refused, []
         if not self.live:
-            return []
+            return refused
         self.ctx.batch_sweep([job for _, job, _ in self.live])
         self.rounds += 1
         self.ctx.synchronize()
@@ -99,7 +122,7 @@ class Server:
             else:
                 keep.append((req, job, adm))
         self.live = keep
-        return out
+        return refused + out
 
     def cancel(self, rid):
         """Drop request `rid`, queued or running (its job is freed); False if
@@ -117,20 +140,21 @@ class Server:
         return False
 
 
-def serve(ctx, requests, budget, clock=time.perf_counter, progress=None, every=50):
+def serve(ctx, requests, budget, clock=time.perf_counter, progress=None, every=50, max_live=0):
     """Run `requests` (with arrival offsets in seconds) through a server
-    with the given byte budget in real time; returns the results in
-    completion order and the server (for its counters).  progress, if
-    given, is called with the number of finished requests every `every`."""
+    with the given byte budget (and at most max_live live jobs, if > 0) in
+    real time; returns the results in completion order and the server (for
+    its counters).  progress, if given, is called with the number of
+    finished requests every `every`."""
     pending = sorted(requests, key=lambda r: r.arrival)
-    srv = Server(ctx, budget)
+    srv = Server(ctx, budget, max_live=max_live)
     t0 = clock()
     now = lambda: clock() - t0
     done = []
-    while pending or srv.queue or srv.live:
+    while pending or srv.queue or srv.live or srv.refused:
         while pending and pending[0].arrival <= now():
-            srv.submit(pending.pop(0))
-        if not srv.queue and not srv.live:
+            srv.submit(pending.pop(0), now())
+        if not srv.queue and not srv.live and not srv.refused:
             time.sleep(max(0.0, min(0.01, pending[0].arrival - now())))
             continue
         before = len(done)

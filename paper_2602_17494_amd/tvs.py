@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtvs.so")
 
 TVS_F32, TVS_F64 = 0, 1
-TVS_EBUSY = -5
+TVS_OK, TVS_EINVAL, TVS_ENOMEM, TVS_EHIP, TVS_ENONFINITE, TVS_EBUSY = 0, -1, -2, -3, -4, -5
 TVS_IRV2, TVS_IRV1 = 0, 1
 TVS_LP_IMAGE, TVS_LP_BLOCKDCT = 0, 1
 

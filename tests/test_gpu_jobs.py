@@ -116,6 +116,38 @@ def test_batch_of_uneven_images(ctx):
         assert np.abs(d_ref.double().cpu().numpy() - d_o).max() < 1e-4
 
 
+def test_batch_mix_of_the_64_image_workload_shapes(ctx):
+    """One job at each side of the 64-image workload (128, 256, 512, 1024)
+    with its layout (4 x 4 with 8-pixel stripes up to 256, 8 x 8 with 8 at
+    512 and 16 at 1024), float32, reduced counts, advanced together: each
+    result equals its one-shot solve bit for bit, and the 128 and 256 images
+    match the FP64 oracle within the float32 bar."""
+    from paper_2602_17494_amd import make_iters, make_layout, make_params
+    specs = [(128, (4, 4, 8, 8)), (256, (4, 4, 8, 8)), (512, (8, 8, 8, 8)), (1024, (8, 8, 16, 16))]
+    its = make_iters(2, 3)
+    jobs, refs, imgs = [], [], []
+    for k, (n, lay) in enumerate(specs):
+        _, d64 = synth.noisy_f32(n, n, 0.1, 400 + k)
+        delta, alpha = synth.params_for_sigma(0.1)
+        d0 = torch.tensor(d64, dtype=torch.float32, device=DEV)
+        prm, L = make_params(delta, alpha), make_layout(*lay)
+        refs.append(one_shot(ctx, d0, prm, L, its))
+        jobs.append(ctx.job(d0, prm, L, its))
+        imgs.append((d64, delta, alpha, lay))
+    run_jobs(ctx, jobs)
+    for job, (d_ref, tau_ref, _) in zip(jobs, refs):
+        d, tau, _ = job.result()
+        torch.cuda.synchronize()
+        assert torch.equal(d, d_ref) and torch.equal(tau, tau_ref)
+        job.close()
+    for (d64, delta, alpha, lay), (d_ref, tau_ref, _) in list(zip(imgs, refs))[:2]:
+        n = d64.shape[0]
+        tau_o, _, _ = osw.step1_schwarz(d64, delta, osw.Layout(n, n, *lay, step=1), 2, 3)
+        d_o, _, _ = osw.step2_schwarz(d64, tau_o, alpha, osw.Layout(n, n, *lay, step=2), 2, 3)
+        assert np.abs(tau_ref.double().cpu().numpy() - tau_o).max() < 1e-5
+        assert np.abs(d_ref.double().cpu().numpy() - d_o).max() < 1e-4
+
+
 def test_serving_loop_interleaves_and_matches_alone(ctx):
     """Poisson arrivals of uneven requests through the continuous-batching
     server with a budget that holds only a few jobs: every result equals the

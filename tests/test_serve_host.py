@@ -85,8 +85,33 @@ def test_admission_within_budget_and_fifo():
 def test_request_over_budget_rejected():
     from paper_2602_17494_amd.serve import Server
     srv = Server(FakeCtx(1), budget=1)
-    with pytest.raises(ValueError):
-        srv.submit(make_requests([64], [0.0])[0])
+    assert not srv.submit(make_requests([64], [0.0])[0])
+    out = srv.round(lambda: 0.0)
+    assert len(out) == 1 and out[0].d is None and "over the budget" in out[0].error
+    assert not srv.queue and not srv.live
+
+
+def test_unsupported_shape_refused_alone():
+    """A request whose shape the library refuses (image sides above 5119) is
+    retired with the library's message; the others are served."""
+    from paper_2602_17494_amd.serve import serve
+    reqs = make_requests([64, 64, 64], [0.0, 0.0, 0.0])
+    reqs[1].d0 = torch.zeros((5120, 64), dtype=torch.float32)
+    ctx = FakeCtx(sweeps=2)
+    results, srv = serve(ctx, reqs, budget=1 << 40)
+    by = {r.rid: r for r in results}
+    assert sorted(by) == [0, 1, 2]
+    assert by[1].d is None and "5120" in by[1].error
+    assert by[0].d is not None and by[2].d is not None
+    assert len(ctx.created) == 2 and srv.in_use == 0
+
+
+def test_max_live_serves_one_at_a_time():
+    from paper_2602_17494_amd.serve import serve
+    ctx = FakeCtx(sweeps=2)
+    results, srv = serve(ctx, make_requests([64] * 4, [0.0] * 4), budget=1 << 40, max_live=1)
+    assert [r.rid for r in results] == [0, 1, 2, 3]
+    assert max(ctx.batches) == 1
 
 
 def test_serve_reports_progress_and_latencies():
