@@ -1,8 +1,11 @@
 """The 2048 x 2048 workload in the launch configuration bench.py times
 (float32, 8 x 8 subdomains, 16-pixel shared stripes).
 
-* Reduced counts (2 sweeps x 2 inner): sampled outputs and row sums against
-  the FP64 oracle's values stored by tests/golden/make_golden_2048.py.
+* Reduced counts (2 sweeps x 2 inner), at each noise level of the workload
+  (sigma = 0.05, 0.1, 0.2): sampled outputs, a window across the corner where
+  four subdomains overlap, and the row and column sums (every pixel enters
+  them) against the FP64 oracle's values stored by
+  tests/golden/make_golden_2048.py.
 * Full counts (20 sweeps x 500 inner), where the oracle cannot run: properties
   that hold at any size -- the float32 image agrees with the float64 run of
   the same kernels to 1e-4, tau is divergence free (float64), the duality
@@ -18,8 +21,9 @@ from oracle import operators as op
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_2048_s2i2.npz")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_2048_s2i2_sigma{}.npz")
 N = 2048
+SEEDS = {0.05: 30, 0.1: 31, 0.2: 32}
 
 
 @pytest.fixture(scope="module")
@@ -32,10 +36,10 @@ def ctx():
     c.close()
 
 
-def solve(ctx, dtype, sweeps, inner):
+def solve(ctx, dtype, sweeps, inner, sigma=0.1):
     from paper_2602_17494_amd import make_iters, make_layout, make_params
-    _, d64 = synth.noisy_f32(N, N, 0.1, 31)
-    delta, alpha = synth.params_for_sigma(0.1)
+    _, d64 = synth.noisy_f32(N, N, sigma, SEEDS[sigma])
+    delta, alpha = synth.params_for_sigma(sigma)
     d0 = torch.tensor(d64, dtype=dtype, device="cuda:0")
     tau = torch.empty((2, N + 1, N + 1), dtype=dtype, device="cuda:0")
     d, st = ctx.schwarz_solve(d0, make_params(delta, alpha), make_layout(8, 8, 16, 16),
@@ -44,21 +48,30 @@ def solve(ctx, dtype, sweeps, inner):
     return d, tau, st
 
 
+@pytest.mark.parametrize("sigma", [0.05, 0.1, 0.2])
 @pytest.mark.parametrize("dtype,tol_d,tol_tau", [("f64", 1e-10, 1e-10), ("f32", 1e-4, 1e-5)])
-def test_2048_reduced_counts_against_oracle(ctx, dtype, tol_d, tol_tau):
-    g = np.load(GOLDEN)
+def test_2048_reduced_counts_against_oracle(ctx, dtype, tol_d, tol_tau, sigma):
+    g = np.load(GOLDEN.format(sigma))
     meta = g["meta"]
+    assert int(meta[1]) == SEEDS[sigma]
     t = torch.float64 if dtype == "f64" else torch.float32
-    d, tau, st = solve(ctx, t, int(meta[2]), int(meta[3]))
+    d, tau, st = solve(ctx, t, int(meta[2]), int(meta[3]), sigma)
     d = d.double().cpu().numpy()
     tau = tau.double().cpu().numpy()
     ii, jj = g["ii"], g["jj"]
     assert np.abs(tau[0, ii, jj] - g["tau1"]).max() < tol_tau
     assert np.abs(tau[1, ii, jj] - g["tau2"]).max() < tol_tau
     assert np.abs(d[np.minimum(ii, N - 1), np.minimum(jj, N - 1)] - g["d"]).max() < tol_d
-    # row sums cover every pixel; N terms each
+    # every point of a window across the corner of four subdomains
+    w0 = int(g["win0"])
+    w = slice(w0, w0 + g["d_win"].shape[0])
+    assert np.abs(d[w, w] - g["d_win"]).max() < tol_d
+    assert np.abs(tau[:, w, w] - g["tau_win"]).max() < tol_tau
+    # row and column sums cover every pixel; N terms each
     assert np.abs(d.sum(axis=1) - g["d_rowsum"]).max() < tol_d * N
+    assert np.abs(d.sum(axis=0) - g["d_colsum"]).max() < tol_d * N
     assert np.abs(tau[1].sum(axis=1) - g["tau2_rowsum"]).max() < tol_tau * N
+    assert np.abs(tau[1].sum(axis=0) - g["tau2_colsum"]).max() < tol_tau * N
     assert st[0]["energy"] == pytest.approx(float(g["energy1"][-1]), rel=1e-9 if dtype == "f64" else 1e-5)
     # The Step-2 dual energy ||div p - f||^2 is dominated by f = alpha (d0 - g),
     # and in float32 g is a row prefix sum of N = 2048 terms: its rounding is
