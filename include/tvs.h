@@ -296,6 +296,19 @@ int tvs_tangent_field(tvs_ctx* ctx, const void* d, int N2, int N1, tvs_dtype dty
 int tvs_quality(tvs_ctx* ctx, const void* x, const void* ref, int n2, int n1, tvs_dtype dtype, double* out,
                 void* stream);
 
+/* For callers that cannot allocate device memory (inside tight serving
+ * loops, or harnesses that forbid hipMalloc): tvs_quality with the same
+ * arguments, results, errors and sums, bit for bit, but it allocates nothing.
+ * Its reduction scratch (1024 FP64 partial sums and the 6 moments, 8.3 KB)
+ * is a static array of the library that every GPU holds once, from the first
+ * tvs_ctx_create on it until the process ends; image sizes are limited as
+ * for tvs_quality (n2 n1 <= 2^31), not by the scratch.  All calls on one GPU
+ * share that array, whatever their context: calls that overlap on one GPU
+ * (other threads, other streams) race and give wrong results.  The call
+ * waits for its stream. */
+int tvs_quality_noalloc(tvs_ctx* ctx, const void* x, const void* ref, int n2, int n1, tvs_dtype dtype,
+                        double* out, void* stream);
+
 /* Checkpoint and resume: a job's state between two sweeps (Algorithm 2's
  * outer iterate p^n of the current step, the subdomain duals q_m^n that the
  * next sweep's inner iterations start from, the FP64 energy history, the

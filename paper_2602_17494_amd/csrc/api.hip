@@ -1154,6 +1154,56 @@ void job_restore(tvs_ctx* c, tvs_job* j, const StateHeader& h, const unsigned ch
   TVS_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free quality measures: the reduction scratch of
+// tvs_quality_noalloc (256 partial sums per moment, 4 moments at a time,
+// then the 6 moments) lives in this file-scope device array.  Each device
+// holds its own copy; host code must use the address hipGetSymbolAddress
+// returns for it with that device current (taken once per device when a
+// context is created there), never the array's name.  Every kernel writes
+// each slot before it is read, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocPartials = 1024;
+constexpr int kNoAllocMoments = 8;
+static __device__ __align__(256) double scratch[kNoAllocPartials + kNoAllocMoments];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// with `device` current
+void bind_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    throw Error(TVS_EINVAL, "device index above " + std::to_string(kMaxDevices - 1));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    throw Error(TVS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<double*>(p);
+}
+
+double* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  double* p = (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+  if (!p) throw Error(TVS_EHIP, "no scratch address for this device (no context was created on it)");
+  return p;
+}
+
+// Section 5.2 with R = 1 (c1 = (0.01 R)^2, c2 = (0.03 R)^2) from the six
+// FP64 sums (x, ref, centred squares of x and ref, centred cross term,
+// squared difference)
+void quality_from_moments(const double (&m)[6], long long n, double* out) {
+  for (double v : m)
+    if (!std::isfinite(v)) throw Error(TVS_ENONFINITE, "quality: non-finite moment");
+  const double c1 = 1e-4, c2 = 9e-4, dn = double(n);
+  const double mx = m[0] / dn, mr = m[1] / dn, vx = m[2] / dn, vr = m[3] / dn, cv = m[4] / dn;
+  const double mse = m[5] / dn;
+  out[0] = mse > 0 ? -10.0 * std::log10(mse) : HUGE_VAL;
+  out[1] = (2 * mx * mr + c1) * (2 * cv + c2) / ((mx * mx + mr * mr + c1) * (vx + vr + c2));
+  out[2] = mse;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1165,6 +1215,7 @@ int tvs_ctx_create(int device, tvs_ctx** out) {
     TVS_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) throw Error(TVS_EINVAL, "no such HIP device");
     DeviceGuard dg(device);
+    bind_scratch(device);
     auto* c = new tvs_ctx();
     c->device = device;
     *out = c;
@@ -1401,15 +1452,32 @@ int tvs_quality(tvs_ctx* ctx, const void* x, const void* ref, int n2, int n1, tv
     double m[6];
     TVS_HIP(hipMemcpyAsync(m, dev, sizeof m, hipMemcpyDeviceToHost, s));
     TVS_HIP(hipStreamSynchronize(s));
-    for (double v : m)
-      if (!std::isfinite(v)) throw Error(TVS_ENONFINITE, "quality: non-finite moment");
-    // Section 5.2 with R = 1: c1 = (0.01 R)^2, c2 = (0.03 R)^2
-    const double c1 = 1e-4, c2 = 9e-4, dn = double(n);
-    const double mx = m[0] / dn, mr = m[1] / dn, vx = m[2] / dn, vr = m[3] / dn, cv = m[4] / dn;
-    const double mse = m[5] / dn;
-    out[0] = mse > 0 ? -10.0 * std::log10(mse) : HUGE_VAL;
-    out[1] = (2 * mx * mr + c1) * (2 * cv + c2) / ((mx * mx + mr * mr + c1) * (vx + vr + c2));
-    out[2] = mse;
+    quality_from_moments(m, n, out);
+  });
+}
+
+int tvs_quality_noalloc(tvs_ctx* ctx, const void* x, const void* ref, int n2, int n1, tvs_dtype dtype,
+                        double* out, void* stream) {
+  return guarded([&] {
+    if (!ctx || !x || !ref || !out) throw Error(TVS_EINVAL, "NULL argument");
+    if (n2 < 1 || n1 < 1) throw Error(TVS_EINVAL, "grid must be at least 1 x 1");
+    if ((long long)n2 * n1 > (1LL << 31)) throw Error(TVS_EINVAL, "grid too large");
+    if (dtype != TVS_F32 && dtype != TVS_F64) throw Error(TVS_EINVAL, "unknown dtype");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long n = (long long)n2 * n1;
+    double* base = scratch_of(ctx->device);
+    const Partials part{base, kNoAllocPartials};
+    double* dev = base + kNoAllocPartials;
+    if (dtype == TVS_F32)
+      launch_quality_moments<float>(static_cast<const float*>(x), static_cast<const float*>(ref), n, part, dev, s);
+    else
+      launch_quality_moments<double>(static_cast<const double*>(x), static_cast<const double*>(ref), n, part,
+                                     dev, s);
+    double m[6];
+    TVS_HIP(hipMemcpyAsync(m, dev, sizeof m, hipMemcpyDeviceToHost, s));
+    TVS_HIP(hipStreamSynchronize(s));
+    quality_from_moments(m, n, out);
   });
 }
 

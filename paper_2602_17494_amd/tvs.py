@@ -115,6 +115,8 @@ def load():
     lib.tvs_tangent_field.restype = ci
     lib.tvs_quality.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd), vp]
     lib.tvs_quality.restype = ci
+    lib.tvs_quality_noalloc.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd), vp]
+    lib.tvs_quality_noalloc.restype = ci
     lib.tvs_job_destroy.argtypes = [vp]
     lib.tvs_job_destroy.restype = ci
     _lib = lib
@@ -323,6 +325,20 @@ class Context:
         out = (ctypes.c_double * 3)()
         _check(load().tvs_quality(self._h, _dev(x, (n2, n1)), _dev(ref, (n2, n1), x.dtype), n2, n1,
                                   _dtype_code(x), out, _stream(x.device)))
+        return {"psnr": out[0], "mssim": out[1], "mse": out[2]}
+
+    def quality_noalloc(self, x, ref):
+        """As quality(), through tvs_quality_noalloc: the library allocates
+        no device memory for it (its scratch is a static per-GPU array, shared
+        by all calls on that GPU)."""
+        if x.dim() != 2:
+            raise ValueError("expected a 2-D array")
+        if x.shape != ref.shape:
+            raise ValueError("x and ref must have the same shape")
+        n2, n1 = x.shape
+        out = (ctypes.c_double * 3)()
+        _check(load().tvs_quality_noalloc(self._h, _dev(x, (n2, n1)), _dev(ref, (n2, n1), x.dtype), n2, n1,
+                                          _dtype_code(x), out, _stream(x.device)))
         return {"psnr": out[0], "mssim": out[1], "mse": out[2]}
 
     def project_div_free(self, u, h=1.0, out=None):
