@@ -26,7 +26,7 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_code_hash_ignores_comments_and_host_file():
+def test_code_hash_ignores_comments_only():
     b = load_bench()
     csrc = os.path.join(ROOT, "paper_2602_17494_amd", "csrc")
     read = {}
@@ -36,8 +36,11 @@ def test_code_hash_ignores_comments_and_host_file():
     h = b.kernel_source_hash(read=read)
     edited = dict(read)
     edited["green.hip"] = "// a comment\n/* and a block\n comment */\n" + read["green.hip"].replace("\n", "\n  ", 3)
-    edited["api.hip"] = read["api.hip"] + "\nint unused_host_symbol;\n"
     assert b.kernel_source_hash(read=edited) == h
+    # the host orchestration decides frame pitch and box geometry: it counts
+    host = dict(read)
+    host["api.hip"] = read["api.hip"] + "\nint unused_host_symbol;\n"
+    assert b.kernel_source_hash(read=host) != h
     edited["kernels.hip"] = read["kernels.hip"] + "\nint changed;\n"
     assert b.kernel_source_hash(read=edited) != h
 
