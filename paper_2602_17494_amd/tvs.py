@@ -128,7 +128,7 @@ EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_byte
             "tvs_timing_reset", "tvs_timing_count", "tvs_timing_get", "tvs_job_footprint",
             "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
             "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state",
-            "tvs_tangent_field", "tvs_quality", "tvs_set_local_projection",
+            "tvs_tangent_field", "tvs_quality", "tvs_quality_noalloc", "tvs_set_local_projection",
             "tvs_energy_history"]
 
 
