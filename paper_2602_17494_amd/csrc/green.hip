@@ -292,6 +292,26 @@ __device__ __forceinline__ const cplx<T>* stage_twiddles(cplx<T>* lds, const cpl
   }
 }
 
+// Row-pass workgroup -> (row group, box).  With xcd_rows the grid is one-
+// dimensional and each XCD (workgroup w runs on XCD w mod 8) takes a
+// contiguous range of the units, row group fastest: the few row pairs that
+// share a 128-byte chunk of a half-spectrum column then meet in one XCD's L2
+// instead of being fetched (and written) once per XCD.  False when idle.
+template <typename T>
+__device__ __forceinline__ bool row_unit(const GreenDev<T>& d, int& qg, int& b) {
+  if (d.xcd_rows) {
+    const int units = d.row_groups * d.nbox, per = (units + 7) / 8;
+    const int u = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (u >= units) return false;
+    qg = u % d.row_groups;
+    b = u / d.row_groups;
+  } else {
+    qg = blockIdx.x;
+    b = blockIdx.y;
+  }
+  return true;
+}
+
 // Row transforms of the source: rows 2m and 2m+1 of div u (zero outside the
 // box) form the real and imaginary parts of one complex sequence; the half
 // spectra of the two rows are separated from the packed result and stored
@@ -311,10 +331,11 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const int b = blockIdx.y;
+  int qg, b;
+  if (!row_unit(d, qg, b)) return;  // whole workgroup idle
   const GreenBox bx = d.boxes[b];
   const int Lj = SL ? SL : d.Lj, Lh = SL ? SL / 2 + 1 : d.Lh, ppw = d.ppw;
-  const int q0 = blockIdx.x * ppw;
+  const int q0 = qg * ppw;
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
   // all NT threads stage the packed rows (the first pass has fewer butterflies
@@ -514,10 +535,11 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* buf = reinterpret_cast<C*>(smem_raw);
-  const int b = blockIdx.y;
+  int qg, b;
+  if (!row_unit(d, qg, b)) return;  // whole workgroup idle
   const GreenBox bx = d.boxes[b];
   const int Lj = SL ? SL : d.Lj, Lh = SL ? SL / 2 + 1 : d.Lh, ppw = d.ppw;
-  const int q0 = blockIdx.x * ppw;
+  const int q0 = qg * ppw;
   if (2 * q0 >= bx.ni) return;
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
   const int scol = SL ? scol_of(SL) : d.scol;
@@ -707,6 +729,11 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   dev_.Lh = Lh;
   dev_.scol = scol;
   dev_.ppw = br.batch;
+  dev_.nbox = nbox;
+  dev_.row_groups = ((rows_max + 1) / 2 + br.batch - 1) / br.batch;
+  // a workgroup writes (and reads back) 2 ppw rows of every half-spectrum
+  // column: below a 128-byte chunk, neighbouring row groups share chunks
+  dev_.xcd_rows = 2 * br.batch * int(sizeof(cplx<T>)) < 128 ? 1 : 0;
   dev_.cpw = bc.batch;
   dev_.fd_Li = make_fastdiv(Li);
   dev_.fd_Lj = make_fastdiv(Lj);
@@ -838,8 +865,9 @@ double GreenPlan<T>::bytes_rows_inv() const {
 template <typename T>
 void GreenPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t s,
                              KernelTimer* timer, const char* tag) {
-  const int row_groups = ((rows_max + 1) / 2 + dev_.ppw - 1) / dev_.ppw;
-  const dim3 gr(row_groups, nbox), gc(nbox, (dev_.Lh + dev_.cpw - 1) / dev_.cpw);
+  const int row_groups = dev_.row_groups;
+  const dim3 gr = dev_.xcd_rows ? dim3(8 * ((row_groups * nbox + 7) / 8)) : dim3(row_groups, nbox);
+  const dim3 gc(nbox, (dev_.Lh + dev_.cpw - 1) / dev_.cpw);
   const size_t lr = lds_rows(), lc = lds_cols();
   const std::string t(tag);
   for_each_variant([&](auto rf, auto cf, auto ri) {

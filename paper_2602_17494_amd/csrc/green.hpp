@@ -76,7 +76,9 @@ struct GreenTable {
 
 template <typename T>
 struct GreenDev {
-  int n2, n1;
+  int n2, n1, nbox;
+  int row_groups;  // row-pass workgroups per box (2 ppw rows each)
+  int xcd_rows;    // 1: row passes use the XCD-contiguous one-dimensional order
   int Li, Lj, Lh;
   int scol;  // column stride of the half spectra S[box][k_j][row]
   int ppw, cpw;
