@@ -54,8 +54,8 @@ def parse():
                     help="instead: a batch of 64 images of uneven sizes as resident jobs, one "
                          "batch call per Schwarz sweep, against solving them one by one")
     ap.add_argument("--serve", action="store_true",
-                    help="instead: Poisson arrivals through the continuous-batching server, "
-                         "against plain single-domain FP64 solves served one at a time")
+                    help="instead: Poisson arrivals (sides 256-4096) through the continuous-batching "
+                         "server, FP32 Schwarz jobs against plain single-domain FP64 jobs")
     ap.add_argument("--requests", type=int, default=24, help="requests in --serve mode")
     ap.add_argument("--lp-compare", action="store_true",
                     help="instead: time one Step-1 inner iteration with the image-method LP_m and "
@@ -118,81 +118,107 @@ def batch_mode(args):
 
 
 def serve_mode(args):
-    """Poisson arrivals, sides uniform in [256, 2048], sigma uniform in
-    [0.05, 0.2], float32 with FP64 reductions, layout M = clamp(round(N/256),
-    1, 8) per axis with s = 16, 10 sweeps x 100 inner per step, admission by
-    footprint within 64 GB.  The same requests are then served one at a time
-    as plain single-domain FP64 solves with 1000 dual iterations per step.
-    The arrival rate is 0.7 of the measured plain-FP64 capacity."""
+    """Serving workload: Poisson arrivals of denoise requests, image side
+    uniform in [256, 4096], sigma uniform in [0.05, 0.2], served twice on the
+    same arrivals, each time through the continuous-batching server
+    (paper_2602_17494_amd.serve, admission by footprint within 64 GB, one
+    batch call per round over all live jobs, 10 sweeps x 100 inner
+    iterations per step):
+      * FP32 Schwarz jobs with FP64 reductions, layout M = clamp(round(N /
+        256), 1, 16) per axis, 16-pixel shared stripes;
+      * the plain single-domain FP64 solve as jobs (layout 1 x 1: 10 x 100
+        is exactly 1000 Chambolle iterations per step).
+    The arrival rate is 0.7 of the plain FP64 capacity, measured first as
+    one-at-a-time plain solves of a sample of sides (fitted to a + b N^2 and
+    averaged over the side distribution).  Latencies are measured in real
+    time for both servers; the device bytes in use are sampled after every
+    round."""
     import numpy as np
     import torch
     import synth
     from paper_2602_17494_amd import Context, make_iters, make_layout, make_params
     from paper_2602_17494_amd.serve import Request, latency_summary, serve
-    ctx = Context(0)
     rng = np.random.default_rng(5)
     its = make_iters(10, 100)
-    its_plain = make_iters(1, 1000)
+    lo, hi = 256, 4096
     specs = []
     for k in range(args.requests):
-        n = int(rng.integers(256, 2049))
+        n = int(rng.integers(lo, hi + 1))
         sigma = float(rng.uniform(0.05, 0.2))
-        m = max(1, min(8, round(n / 256)))
+        m = max(1, min(16, round(n / 256)))
         specs.append((k, n, sigma, m))
-    imgs = {}
-    for k, n, sigma, m in specs:
-        imgs[k], _ = synth.noisy_f32(n, n, sigma, 5000 + k)
-    # plain FP64 capacity: time each request's plain solve (warm plans first),
-    # each in a context of its own so that plans of many sizes are not kept
-    plain_t = {}
-    for i, (k, n, sigma, m) in enumerate(specs):
-        delta, alpha = synth.params_for_sigma(sigma)
-        d0 = torch.tensor(imgs[k], dtype=torch.float64, device="cuda:0")
-        with Context(0) as pc:
-            pc.schwarz_solve(d0, make_params(delta, alpha), make_layout(), make_iters(1, 1), stats=False)
+    # plain FP64 capacity: one-at-a-time solves of a sample of sides
+    sample_n = [256, 768, 1280, 1792, 2304, 2816, 3328, 3840, 4096]
+    ts = []
+    with Context(0) as pc:
+        for n in sample_n:
+            _, d64 = synth.noisy_f32(n, n, 0.1, 90 + n)
+            d0 = torch.tensor(d64, dtype=torch.float64, device="cuda:0")
+            prm = make_params(*synth.params_for_sigma(0.1))
+            pc.schwarz_solve(d0, prm, make_layout(), make_iters(1, 1), stats=False)  # plans
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            pc.schwarz_solve(d0, make_params(delta, alpha), make_layout(), its_plain, stats=False)
+            pc.schwarz_solve(d0, prm, make_layout(), its, stats=False)
             torch.cuda.synchronize()
-            plain_t[k] = time.perf_counter() - t0
-        if (i + 1) % 50 == 0:
-            print(f"serve: plain FP64 service times measured for {i + 1} of {len(specs)} requests",
-                  file=sys.stderr, flush=True)
-    mean_service = float(np.mean(list(plain_t.values())))
+            ts.append(time.perf_counter() - t0)
+            del d0
+            print(f"serve: plain FP64 service time at {n}^2: {ts[-1]:.3f} s", file=sys.stderr, flush=True)
+    coef = np.polyfit(np.array(sample_n, dtype=float) ** 2, np.array(ts), 1)
+    mean_service = float(np.mean([np.polyval(coef, float(n) ** 2) for _, n, _, _ in specs]))
     rate = 0.7 / mean_service
     arrivals, t = [], 0.0
     for _ in specs:
         t += float(rng.exponential(1.0 / rate))
         arrivals.append(t)
-    # the plain FP64 server: FIFO, one request at a time (service times measured above)
-    free, lat_plain = 0.0, []
-    for (k, *_), a in zip(specs, arrivals):
-        start = max(free, a)
-        free = start + plain_t[k]
-        lat_plain.append(free - a)
-    reqs = []
-    for (k, n, sigma, m), a in zip(specs, arrivals):
-        delta, alpha = synth.params_for_sigma(sigma)
-        d0 = torch.tensor(imgs[k], dtype=torch.float32, device="cuda:0")
-        lay = make_layout(m, m, 16 if m > 1 else 0, 16 if m > 1 else 0)
-        reqs.append(Request(k, d0, make_params(delta, alpha), lay, its, arrival=a))
-    t0 = time.perf_counter()
-    results, srv = serve(ctx, reqs, 64 << 30,
-                         progress=lambda done: print(f"serve: {done} of {len(reqs)} requests served",
-                                                     file=sys.stderr, flush=True))
-    wall = time.perf_counter() - t0
-    pix = sum(((n + 1) ** 2 + n * n) for _, n, _, _ in specs) * 10 * 100
-    lat = latency_summary(results)
-    out = {"metric": "continuous-batching serving, FP32 Schwarz jobs (10 sweeps x 100 inner per step)",
-           "requests": len(results), "rate_per_s": round(rate, 3),
-           "throughput_mpix_iter_s": round(pix / wall / 1e6, 1),
-           "latency_s": {"p50": round(lat["p50"], 4), "p99": round(lat["p99"], 4)},
-           "rounds": srv.rounds, "peak_bytes": srv.peak_in_use,
-           "plain_fp64_fifo": {"latency_s": {"p50": round(float(np.percentile(lat_plain, 50)), 4),
-                                              "p99": round(float(np.percentile(lat_plain, 99)), 4)},
-                               "mean_service_s": round(mean_service, 4),
-                               "dual_iterations_per_step": 1000},
-           "data": "synthetic"}
+    imgs = {k: synth.noisy_f32(n, n, sigma, 5000 + k)[0] for k, n, sigma, _ in specs}
+    free0, total_mem = torch.cuda.mem_get_info(0)
+
+    def used():
+        return free0 - torch.cuda.mem_get_info(0)[0]
+
+    def run(kind):
+        reqs = []
+        for (k, n, sigma, m), a in zip(specs, arrivals):
+            delta, alpha = synth.params_for_sigma(sigma)
+            if kind == "fp32_schwarz":
+                d0 = torch.tensor(imgs[k], dtype=torch.float32, device="cuda:0")
+                lay = make_layout(m, m, 16 if m > 1 else 0, 16 if m > 1 else 0)
+            else:
+                d0 = torch.tensor(imgs[k], dtype=torch.float64, device="cuda:0")
+                lay = make_layout()
+            reqs.append(Request(k, d0, make_params(delta, alpha), lay, its, arrival=a))
+        torch.cuda.synchronize()
+        with Context(0) as ctx:
+            t0 = time.perf_counter()
+            results, srv = serve(ctx, reqs, 64 << 30, probe=used,
+                                 progress=lambda done: print(f"serve {kind}: {done} of {len(reqs)} requests "
+                                                             "served", file=sys.stderr, flush=True), every=10)
+            wall = time.perf_counter() - t0
+        ok = [r for r in results if not r.error]
+        pix = sum(((r.d.shape[0] + 1) ** 2 + r.d.shape[0] ** 2) for r in ok) * 10 * 100
+        lat = latency_summary(ok)
+        rec = {"served": len(ok), "refused_or_failed": len(results) - len(ok),
+               "latency_s": {"p50": round(lat["p50"], 4), "p99": round(lat["p99"], 4),
+                             "mean": round(lat["mean"], 4)},
+               "throughput_mpix_iter_s": round(pix / wall / 1e6, 1), "wall_s": round(wall, 2),
+               "rounds": srv.rounds, "peak_footprint_bytes": srv.peak_in_use,
+               "peak_device_bytes_measured": int(srv.peak_probe)}
+        del reqs, results
+        torch.cuda.synchronize()
+        return rec
+
+    fp32 = run("fp32_schwarz")
+    plain = run("fp64_plain")
+    out = {"metric": "continuous-batching serving: p50/p99 latency and throughput, FP32 Schwarz jobs against "
+                     "plain single-domain FP64 jobs on the same arrivals",
+           "requests": len(specs), "sides": [lo, hi], "rate_per_s": round(rate, 4),
+           "plain_fp64_mean_service_s": round(mean_service, 4),
+           "plain_fp64_service_fit_s": {"a": float(coef[1]), "b_per_px": float(coef[0])},
+           "iterations_per_step": "10 sweeps x 100 inner",
+           "fp32_schwarz": fp32, "fp64_plain": plain,
+           "p99_speedup": round(plain["latency_s"]["p99"] / fp32["latency_s"]["p99"], 2),
+           "throughput_speedup": round(fp32["throughput_mpix_iter_s"] / plain["throughput_mpix_iter_s"], 2),
+           "device_bytes_total": int(total_mem), "data": "synthetic"}
     print(json.dumps(out), flush=True)
 
 

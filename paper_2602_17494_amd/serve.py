@@ -59,6 +59,7 @@ class Server:
     peak_in_use: int = 0
     rounds: int = 0
     max_live: int = 0                 # > 0: at most this many live jobs
+    peak_probe: int = 0               # largest value of serve()'s probe
     refused: list = field(default_factory=list)  # results of refused requests, not yet returned
 
     def _refuse(self, req, now, msg):
@@ -140,12 +141,14 @@ class Server:
         return False
 
 
-def serve(ctx, requests, budget, clock=time.perf_counter, progress=None, every=50, max_live=0):
+def serve(ctx, requests, budget, clock=time.perf_counter, progress=None, every=50, max_live=0, probe=None):
     """Run `requests` (with arrival offsets in seconds) through a server
     with the given byte budget (and at most max_live live jobs, if > 0) in
     real time; returns the results in completion order and the server (for
     its counters).  progress, if given, is called with the number of
-    finished requests every `every`."""
+    finished requests every `every`; probe, if given, after every round,
+    and the largest value it returns is kept as srv.peak_probe (for example
+    the device bytes in use)."""
     pending = sorted(requests, key=lambda r: r.arrival)
     srv = Server(ctx, budget, max_live=max_live)
     t0 = clock()
@@ -159,6 +162,8 @@ def serve(ctx, requests, budget, clock=time.perf_counter, progress=None, every=5
             continue
         before = len(done)
         done.extend(srv.round(now))
+        if probe is not None:
+            srv.peak_probe = max(srv.peak_probe, probe())
         if progress and len(done) // every > before // every:
             progress(len(done))
     return done, srv
