@@ -57,6 +57,8 @@ def parse():
                     help="instead: Poisson arrivals (sides 256-4096) through the continuous-batching "
                          "server, FP32 Schwarz jobs against plain single-domain FP64 jobs")
     ap.add_argument("--requests", type=int, default=24, help="requests in --serve mode")
+    ap.add_argument("--timing", action="store_true",
+                    help="--batch: time one launch in 16 of each kernel class (eager launches, no graphs)")
     ap.add_argument("--burst", type=int, default=24,
                     help="--serve: requests of the capacity (burst) runs, the first of the Poisson ones")
     ap.add_argument("--lp-compare", action="store_true",
@@ -98,6 +100,10 @@ def batch_mode(args):
     # as jobs: creation (plans, copies) outside the timed region
     jobs = [ctx.job(d0, prm, lay, its) for d0, prm, lay in work]
     torch.cuda.synchronize()
+    if args.timing:
+        # per-class kernel times (launched eagerly: no graph while timing)
+        ctx.timing_reset()
+        ctx.timing(True, every=TIMING_EVERY)
     t0 = time.perf_counter()
     calls = 0
     while True:
@@ -108,12 +114,20 @@ def batch_mode(args):
         calls += 1
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    kernels = None
+    if args.timing:
+        ctx.timing(False)
+        kernels = {k: {"timed_launches": v[0], "avg_us": round(v[1] / v[0] * 1e3, 2) if v[0] else None,
+                       "total_ms_est": round(v[1] * TIMING_EVERY, 1)}
+                   for k, v in sorted(ctx.timing_read().items(), key=lambda kv: -kv[1][1])}
     out = {"metric": "Mpix*iter/s, batch of 64 uneven images (FP32 Schwarz, both steps)",
            "value": round(pix / t_batch / 1e6, 1), "unit": "Mpix*iter/s",
            "seconds": round(t_batch, 3), "batch_calls": calls,
            "one_by_one": {"seconds": round(t_seq, 3), "mpix_iter_s": round(pix / t_seq / 1e6, 1)},
            "megapixels": round(sum(d.numel() for d, _, _ in work) / 1e6, 2),
            "sweeps": args.sweeps, "inner": args.inner, "dtype": "f32", "data": "synthetic"}
+    if kernels is not None:
+        out["kernels"] = kernels
     for j in jobs:
         j.close()
     print(json.dumps(out), flush=True)

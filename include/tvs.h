@@ -205,16 +205,20 @@ int tvs_timing_get(tvs_ctx* ctx, int i, char* name, int name_len, long long* lau
  *                      job's state, copy d0 (device pointer, N2 x N1; the
  *                      caller may reuse it on return) and run the Step-1
  *                      set-up on `stream`; the call waits for that work
- *   tvs_batch_sweep    advance each of the n jobs (of this context) by one
- *                      sweep of its current step, ordered after the work
- *                      already on `stream`, and make `stream` wait for it;
- *                      with several jobs the context spreads them over up to
- *                      4 streams of its own, so that their kernels overlap
- *                      on the device.  The part of a sweep that is the same
- *                      in every sweep (the subdomain prologue, the inner
- *                      iterations and the combination) is recorded as a HIP
- *                      graph the first time and replayed afterwards, unless
- *                      kernel timing is on.  The sweep that completes Step 1 also
+ *   tvs_batch_sweep    advance each of the n jobs (of this context, each at
+ *                      most once in the list) by one sweep of its current
+ *                      step, ordered after the work already on `stream`, and
+ *                      make `stream` wait for it.  The work runs on a stream
+ *                      of the context: first every job's sweep head (the
+ *                      global residual and FP64 energy, and the stopping
+ *                      test), then the sweep bodies of all jobs, recorded
+ *                      as one HIP graph and replayed while the same jobs
+ *                      come in the same states (eagerly while kernel timing
+ *                      is on).  In the bodies, jobs of one shape (step,
+ *                      dtype, image size, layout, h, t and inner count)
+ *                      run each inner iteration as one launch per kernel
+ *                      class over the subdomains of all of them.  The sweep
+ *                      that completes Step 1 also
  *                      computes tau and its statistics (which waits for that
  *                      job's work) and sets up Step 2; the one that completes
  *                      Step 2 computes d.  A finished job is left as it is.

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -242,14 +243,21 @@ struct tvs_ctx {
   size_t scal_cap = 0;
   // streams a batch call spreads independent jobs over (default priority),
   // with the events that fork them from and join them to the caller's stream
-  static constexpr int kBatchStreams = 4;
-  hipStream_t bstream[kBatchStreams] = {};
-  hipEvent_t bfork = nullptr, bjoin[kBatchStreams] = {};
+  // the stream a batch call runs its work on (default priority), forked
+  // from and joined to the caller's stream, which may be the legacy default
+  // stream (not capturable)
+  hipStream_t bstream = nullptr;
+  hipEvent_t bfork = nullptr, bjoin = nullptr;
+  // JobBufs tables of the last batch call, and its sweep bodies recorded as
+  // one graph, with the key (job uid, step, ping-pong state, per job) it was
+  // recorded for
+  tvs::DevBuf jobtab;
+  std::vector<unsigned long long> bkey;
+  hipGraphExec_t bgraph = nullptr;
   ~tvs_ctx() {
-    for (int k = 0; k < kBatchStreams; ++k) {
-      if (bstream[k]) (void)hipStreamDestroy(bstream[k]);
-      if (bjoin[k]) (void)hipEventDestroy(bjoin[k]);
-    }
+    if (bgraph) (void)hipGraphExecDestroy(bgraph);
+    if (bstream) (void)hipStreamDestroy(bstream);
+    if (bjoin) (void)hipEventDestroy(bjoin);
     if (bfork) (void)hipEventDestroy(bfork);
   }
 };
@@ -548,42 +556,68 @@ struct Step1Run {
   // caller may record them once in a graph and replay it; with launch =
   // false only the host-side state advances (the graph did the work).
   void body(hipStream_t s, bool launch) {
+    if (launch) {
+      prologue(s);
+      for (int nu = 0; nu < its.inner; ++nu) {
+        inner(s);
+        std::swap(cur, nxt);
+        std::swap(zcur, znxt);
+      }
+      combine(s);
+    } else {
+      for (int nu = 0; nu < its.inner; ++nu) {
+        std::swap(cur, nxt);
+        std::swap(zcur, znxt);
+      }
+    }
+    ++done;
+    ++n;
+    if (n >= its.sweeps) finished = true;
+  }
+  // a2's subdomain part: omega_m = R_{m,+} r^n + LP_m(vecdiv(theta_m p^n))
+  void prologue(hipStream_t s) {
+    if (P->plain) return;
     const Grid g = P->g;
     const SubFrames& sf = P->ss.sf;
     const T inv_h = cs.inv_h;
     const Frame f2p = sub_frame(sf, 2), f1p = sub_frame(sf, 1);
+    launch_sub_theta_p<T>(sf, g, dptr<T>(P->p), 4, dptr<T>(P->vt), s);
+    launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P->vt), dptr<T>(P->zw), s);
+    local_apply(dptr<T>(P->zw), f2p, dptr<T>(P->phi), f1p, s, "s1_local");
+    launch_sub_omega<T>(sf, g, inv_h, dptr<T>(P->r), dptr<T>(P->zw), dptr<T>(P->phi), dptr<T>(P->omega), s);
+  }
+  // a3: one inner iteration, warm-started from the previous sweep's q_m:
+  // phi = Delta^+ div z on the Green box, the update of v, z' = vecdiv v'
+  void inner(hipStream_t s) {
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
+    const Frame f2p = sub_frame(sf, 2), f1p = sub_frame(sf, 1);
+    const double px = P->ss.sub_px, esz = sizeof(T);
+    local_apply(zcur, f2p, dptr<T>(P->phi), f1p, s, P->plain ? "s1_plain" : "s1_local");
+    KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
+      launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P->phi), dptr<T>(P->omega), nxt, s);
+    });
+    KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
+                      [&] { launch_sub_vecdiv<T>(sf, g, cs.inv_h, nxt, znxt, s); });
+  }
+  // a4: p^{n+1} = (1 - ahat) p^n + ahat sum_m q_m, with q_m the state the
+  // inner iterations ended in (`ahead` iterations after `cur`)
+  void combine(hipStream_t s, int ahead = 0) {
+    const Grid g = P->g;
+    const SubFrames& sf = P->ss.sf;
     const long long gpl = (long long)g.n2 * g.n1;
     const double px = P->ss.sub_px, esz = sizeof(T);
-    const char* ltag = P->plain ? "s1_plain" : "s1_local";
-    const T* omega = dptr<T>(P->omega);
-    if (launch && !P->plain) {
-      // omega_m = R_{m,+} r^n + LP_m(vecdiv(theta_m p^n))
-      launch_sub_theta_p<T>(sf, g, dptr<T>(P->p), 4, dptr<T>(P->vt), s);
-      launch_sub_vecdiv<T>(sf, g, inv_h, dptr<T>(P->vt), dptr<T>(P->zw), s);
-      local_apply(dptr<T>(P->zw), f2p, dptr<T>(P->phi), f1p, s, ltag);
-      launch_sub_omega<T>(sf, g, inv_h, dptr<T>(P->r), dptr<T>(P->zw), dptr<T>(P->phi), dptr<T>(P->omega), s);
-    }
-    // a3: inner iterations, warm-started from the previous sweep's q_m:
-    // phi = Delta^+ div z on the Green box, the update of v, z' = vecdiv v'
-    for (int nu = 0; nu < its.inner; ++nu) {
-      if (launch) {
-        local_apply(zcur, f2p, dptr<T>(P->phi), f1p, s, ltag);
-        KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
-          launch_sub_update1<T>(sf, g, cs, cur, zcur, dptr<T>(P->phi), omega, nxt, s);
-        });
-        KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s,
-                          [&] { launch_sub_vecdiv<T>(sf, g, inv_h, nxt, znxt, s); });
-      }
-      std::swap(cur, nxt);
-      std::swap(zcur, znxt);
-    }
-    // a4: p^{n+1} = (1 - ahat) p^n + ahat sum_m q_m
-    if (launch)
-      KernelTimer::time(tm, "s1_combine", 4 * esz * (2.0 * gpl + px), s,
-                        [&] { launch_combine<T>(sf, g, 4, cs.ahat, cur, dptr<T>(P->p), s); });
-    ++done;
-    ++n;
-    if (n >= its.sweeps) finished = true;
+    const T* q = (ahead & 1) ? nxt : cur;
+    KernelTimer::time(tm, "s1_combine", 4 * esz * (2.0 * gpl + px), s,
+                      [&] { launch_combine<T>(sf, g, 4, cs.ahat, q, dptr<T>(P->p), s); });
+  }
+  // the Green plan of the inner iterations
+  GreenPlan<T>& inner_plan() const { return P->plain ? *P->global : *P->local; }
+  // this run's buffers for a batched inner iteration
+  JobBufs<T> bufs() const {
+    GreenPlan<T>& gp = inner_plan();
+    return JobBufs<T>{{dptr<T>(P->va), dptr<T>(P->vb)}, {dptr<T>(P->za), dptr<T>(P->zb)}, dptr<T>(P->phi),
+                      dptr<T>(P->omega), gp.S_ptr(), gp.spec_ptr(), parity(), 0};
   }
   // which of the two ping-pong states the next body starts from
   int parity() const { return cur == dptr<T>(P->va) ? 0 : 1; }
@@ -706,26 +740,37 @@ struct Step2Run {
 
   // a7-a9, the same launches in every sweep (see Step1Run::body)
   void body(hipStream_t s, bool launch) {
-    const Grid g = P->g;
-    const SubFrames& sf = P->ss.sf;
-    const long long gpl = (long long)N2 * N1;
-    const double px = P->ss.sub_px, esz = sizeof(T);
-    // a7: b_m = div((1 - theta_m) p^n) - f near the subdomain
-    if (launch) launch_sub2_prologue<T>(sf, g, cs.inv_h, dptr<T>(P->p), dptr<T>(P->f2), dptr<T>(P->b), s);
-    // a8: inner iterations
+    if (launch) prologue(s);
     for (int nu = 0; nu < its.inner; ++nu) {
-      if (launch)
-        KernelTimer::time(tm, "s2_update", 5 * esz * px, s,
-                          [&] { launch_sub2_update<T>(sf, g, cs, cur, dptr<T>(P->b), nxt, s); });
+      if (launch) inner(s);
       std::swap(cur, nxt);
     }
-    // a9: combine
-    if (launch)
-      KernelTimer::time(tm, "s2_combine", 2 * esz * (2.0 * gpl + px), s,
-                        [&] { launch_combine<T>(sf, g, 2, cs.ahat, cur, dptr<T>(P->p), s); });
+    if (launch) combine(s);
     ++done;
     ++n;
     if (n >= its.sweeps) finished = true;
+  }
+  // a7: b_m = div((1 - theta_m) p^n) - f near the subdomain
+  void prologue(hipStream_t s) {
+    launch_sub2_prologue<T>(P->ss.sf, P->g, cs.inv_h, dptr<T>(P->p), dptr<T>(P->f2), dptr<T>(P->b), s);
+  }
+  // a8: one inner iteration
+  void inner(hipStream_t s) {
+    const double px = P->ss.sub_px, esz = sizeof(T);
+    KernelTimer::time(tm, "s2_update", 5 * esz * px, s,
+                      [&] { launch_sub2_update<T>(P->ss.sf, P->g, cs, cur, dptr<T>(P->b), nxt, s); });
+  }
+  // a9: combine (the state `ahead` inner iterations after `cur`)
+  void combine(hipStream_t s, int ahead = 0) {
+    const long long gpl = (long long)N2 * N1;
+    const double px = P->ss.sub_px, esz = sizeof(T);
+    const T* q = (ahead & 1) ? nxt : cur;
+    KernelTimer::time(tm, "s2_combine", 2 * esz * (2.0 * gpl + px), s,
+                      [&] { launch_combine<T>(P->ss.sf, P->g, 2, cs.ahat, q, dptr<T>(P->p), s); });
+  }
+  JobBufs<T> bufs() const {
+    return JobBufs<T>{{dptr<T>(P->va), dptr<T>(P->vb)}, {nullptr, nullptr}, nullptr, dptr<T>(P->b), nullptr,
+                      nullptr, parity(), 0};
   }
   int parity() const { return cur == dptr<T>(P->va) ? 0 : 1; }
 
@@ -826,17 +871,9 @@ struct JobState {
   std::unique_ptr<Step2Problem<T>> p2;
   std::unique_ptr<Step1Run<T>> r1;
   std::unique_ptr<Step2Run<T>> r2;
-  // the sweep bodies of both steps recorded as graphs, per ping-pong parity
-  hipGraphExec_t g1[2] = {}, g2[2] = {};
   JobState() = default;
   JobState(const JobState&) = delete;
   JobState& operator=(const JobState&) = delete;
-  ~JobState() {
-    for (int k = 0; k < 2; ++k) {
-      if (g1[k]) (void)hipGraphExecDestroy(g1[k]);
-      if (g2[k]) (void)hipGraphExecDestroy(g2[k]);
-    }
-  }
   size_t bytes() const {
     return d0.bytes + tau.bytes + dout.bytes + part.bytes + e1.bytes + e2.bytes + p1->bytes() +
            p2->bytes();
@@ -876,6 +913,7 @@ size_t job_bytes_estimate(int N2, int N1, const tvs_layout* l, int sweeps) {
 
 struct tvs_job {
   tvs_ctx* ctx = nullptr;
+  unsigned long long uid = 0;  // unique within the process (batch-graph keys)
   tvs_dtype dtype = TVS_F32;
   int N2 = 0, N1 = 0;
   tvs_params prm{};
@@ -892,6 +930,11 @@ struct tvs_job {
 using namespace tvs;
 
 namespace {
+
+unsigned long long next_job_uid() {
+  static std::atomic<unsigned long long> uid{0};
+  return ++uid;
+}
 
 template <typename T>
 JobState<T>& job_state(tvs_job* j);
@@ -926,42 +969,6 @@ void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s,
     j->d = std::move(st);
 }
 
-// One sweep of a run: its head eagerly, its body from a graph recorded the
-// first time the body starts from this ping-pong parity (the recording is
-// then launched once to do the work).  Without graphs (kernel timing on, so
-// that every launch keeps its own events) the body runs eagerly.
-template <typename Run>
-bool graph_sweep(Run& run, hipGraphExec_t (&gx)[2], bool graphs, hipStream_t s) {
-  if (!run.head(s)) return false;
-  if (!graphs) {
-    run.body(s, true);
-    return !run.finished;
-  }
-  const int par = run.parity();
-  if (gx[par]) {
-    TVS_HIP(hipGraphLaunch(gx[par], s));
-    run.body(s, false);
-    return !run.finished;
-  }
-  hipGraph_t g = nullptr;
-  TVS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  try {
-    run.body(s, true);
-  } catch (...) {
-    (void)hipStreamEndCapture(s, &g);
-    if (g) (void)hipGraphDestroy(g);
-    throw;
-  }
-  TVS_HIP(hipStreamEndCapture(s, &g));
-  hipGraphExec_t ex = nullptr;
-  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) throw Error(TVS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  gx[par] = ex;
-  TVS_HIP(hipGraphLaunch(ex, s));
-  return !run.finished;
-}
-
 template <typename T>
 void make_run2(tvs_ctx* c, tvs_job* j, JobState<T>& st) {
   st.r2 = std::make_unique<Step2Run<T>>(*st.p2, st.d0.template as<T>(), j->N2, j->N1, &j->prm, &j->lay, &j->its,
@@ -969,25 +976,138 @@ void make_run2(tvs_ctx* c, tvs_job* j, JobState<T>& st) {
                                         st.e2.template as<double>(), &c->timer);
 }
 
-// one sweep of the job's current step; the step's end (and the next step's
-// begin) follow the sweep that completes it
+// The end of a step that has no sweep left (tau and its statistics, then
+// the set-up of Step 2; or the image and the statistics of Step 2).
 template <typename T>
-void job_sweep(tvs_ctx* c, tvs_job* j, hipStream_t s) {
+void job_step_end(tvs_ctx* c, tvs_job* j, hipStream_t s) {
   JobState<T>& st = job_state<T>(j);
-  const bool graphs = !c->timer.on;
   if (j->step == 1) {
-    if (!graph_sweep(*st.r1, st.g1, graphs, s)) {
-      st.r1->end(st.tau.template as<T>(), &j->st[0], s);
-      make_run2(c, j, st);
-      st.r2->begin(st.tau.template as<T>(), s);
-      j->step = 2;
-    }
+    st.r1->end(st.tau.template as<T>(), &j->st[0], s);
+    make_run2(c, j, st);
+    st.r2->begin(st.tau.template as<T>(), s);
+    j->step = 2;
   } else if (j->step == 2) {
-    if (!graph_sweep(*st.r2, st.g2, graphs, s)) {
-      st.r2->end(st.dout.template as<T>(), &j->st[1], s);
-      j->step = 3;
+    st.r2->end(st.dout.template as<T>(), &j->st[1], s);
+    j->step = 3;
+  }
+}
+
+// The head of the job's current step (the FP64 energy and the stopping
+// test); when the stopping test ends the step, its end instead.  True when
+// the job's body is to run in this batch call.
+template <typename T>
+bool job_head(tvs_ctx* c, tvs_job* j, hipStream_t s) {
+  JobState<T>& st = job_state<T>(j);
+  if (j->step == 1 ? st.r1->head(s) : j->step == 2 ? st.r2->head(s) : false) return true;
+  job_step_end<T>(c, j, s);
+  return false;
+}
+
+// After a body: the end of the step if that was its last sweep.
+template <typename T>
+void job_after(tvs_ctx* c, tvs_job* j, hipStream_t s) {
+  JobState<T>& st = job_state<T>(j);
+  if ((j->step == 1 && st.r1->finished) || (j->step == 2 && st.r2->finished)) job_step_end<T>(c, j, s);
+}
+
+// Jobs whose sweep bodies run together.  Jobs of one group share the step,
+// the dtype, the image shape, the layout, h, t and the inner count, hence
+// every geometric descriptor: their inner iterations run as one launch per
+// kernel class over all their subdomains (JobBufs tables).
+struct BodyGroup {
+  int step, dtype;
+  std::vector<tvs_job*> jobs;
+  size_t table_off = 0;  // byte offset of the group's JobBufs table
+};
+
+using GroupKey = std::tuple<int, int, int, int, int, int, int, int, double, double, int>;
+GroupKey group_key(const tvs_job* j) {
+  return GroupKey{j->step, int(j->dtype), j->N2, j->N1, j->lay.M2, j->lay.M1, j->lay.s_y, j->lay.s_x,
+                  j->prm.h, j->prm.t, j->its.inner};
+}
+
+template <typename T>
+JobBufs<T> job_bufs(tvs_job* j) {
+  JobState<T>& st = job_state<T>(j);
+  return j->step == 1 ? st.r1->bufs() : st.r2->bufs();
+}
+
+// One inner iteration (index nu) of every job of a group, one launch per
+// kernel class; `table` is the group's JobBufs array on the device.
+template <typename T>
+void group_inner(const BodyGroup& G, const JobBufs<T>* table, int nu, KernelTimer* tm, hipStream_t s) {
+  const int nj = int(G.jobs.size()), flip = nu & 1;
+  JobState<T>& st0 = job_state<T>(G.jobs[0]);
+  const double esz = sizeof(T);
+  if (G.step == 1) {
+    Step1Run<T>& r = *st0.r1;
+    const SubFrames& sf = r.P->ss.sf;
+    const double px = r.P->ss.sub_px * nj;
+    r.inner_plan().apply_div_jobs(table, nj, flip, sub_frame(sf, 2), sub_frame(sf, 1), s, tm,
+                                  r.P->plain ? "s1_plain" : "s1_local");
+    KernelTimer::time(tm, "s1_update", 13 * esz * px, s, [&] {
+      launch_sub_update1_jobs<T>(sf, r.P->g, r.cs, JobRef<T>{table, sf.nsub, flip}, nj, s);
+    });
+    KernelTimer::time(tm, "s1_vecdiv", 6 * esz * px, s, [&] {
+      launch_sub_vecdiv_jobs<T>(sf, r.P->g, r.cs.inv_h, JobRef<T>{table, sf.nsub, flip ^ 1}, nj, s);
+    });
+  } else {
+    Step2Run<T>& r = *st0.r2;
+    const SubFrames& sf = r.P->ss.sf;
+    KernelTimer::time(tm, "s2_update", 5 * esz * r.P->ss.sub_px * nj, s, [&] {
+      launch_sub2_update_jobs<T>(sf, r.P->g, r.cs, JobRef<T>{table, sf.nsub, flip}, nj, s);
+    });
+  }
+}
+
+template <typename T>
+void job_prologue(tvs_job* j, hipStream_t s) {
+  JobState<T>& st = job_state<T>(j);
+  if (j->step == 1) st.r1->prologue(s);
+  else st.r2->prologue(s);
+}
+// the combination, launched before the host state advances: the inner
+// iterations ended `inner` ping-pong steps after the current state
+template <typename T>
+void job_combine(tvs_job* j, hipStream_t s) {
+  JobState<T>& st = job_state<T>(j);
+  if (j->step == 1) st.r1->combine(s, j->its.inner);
+  else st.r2->combine(s, j->its.inner);
+}
+// the host-side state of a body that ran (ping-pong parity, counters)
+template <typename T>
+void job_advance(tvs_job* j) {
+  JobState<T>& st = job_state<T>(j);
+  if (j->step == 1) st.r1->body(nullptr, false);
+  else st.r2->body(nullptr, false);
+}
+
+// The sweep bodies of all groups: every job's prologue, then the inner
+// iterations group by group, nu by nu, then every job's combination.
+void launch_bodies(tvs_ctx* c, const std::vector<BodyGroup>& groups, hipStream_t s) {
+  KernelTimer* tm = &c->timer;
+  int inner = 0;
+  for (const BodyGroup& G : groups) {
+    inner = std::max(inner, G.jobs[0]->its.inner);
+    for (tvs_job* j : G.jobs) {
+      if (G.dtype == TVS_F32) job_prologue<float>(j, s);
+      else job_prologue<double>(j, s);
     }
   }
+  const char* base = static_cast<const char*>(c->jobtab.p);
+  for (int nu = 0; nu < inner; ++nu)
+    for (const BodyGroup& G : groups) {
+      if (nu >= G.jobs[0]->its.inner) continue;
+      if (G.dtype == TVS_F32)
+        group_inner<float>(G, reinterpret_cast<const JobBufs<float>*>(base + G.table_off), nu, tm, s);
+      else
+        group_inner<double>(G, reinterpret_cast<const JobBufs<double>*>(base + G.table_off), nu, tm, s);
+    }
+  for (const BodyGroup& G : groups)
+    for (tvs_job* j : G.jobs) {
+      if (G.dtype == TVS_F32) job_combine<float>(j, s);
+      else job_combine<double>(j, s);
+    }
 }
 
 // ---- a job's state between sweeps, as one host blob (checkpoint/resume) ----
@@ -1511,6 +1631,7 @@ int tvs_job_create(tvs_ctx* ctx, const void* d0, int N2, int N1, tvs_dtype dtype
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto j = std::make_unique<tvs_job>();
     j->ctx = ctx;
+    j->uid = next_job_uid();
     j->dtype = dtype;
     j->N2 = N2;
     j->N1 = N1;
@@ -1532,48 +1653,138 @@ int tvs_batch_sweep(tvs_ctx* ctx, tvs_job* const* jobs, int n, void* stream) {
     if (!ctx || (n > 0 && !jobs) || n < 0) throw Error(TVS_EINVAL, "bad job list");
     for (int i = 0; i < n; ++i)
       if (!jobs[i] || jobs[i]->ctx != ctx) throw Error(TVS_EINVAL, "job missing or of another context");
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < i; ++k)
+        if (jobs[k] == jobs[i]) throw Error(TVS_EINVAL, "a job appears twice in the list");
+    if (n == 0) return;
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // a job whose FP64 statistics come out non-finite fails alone: it is
-    // marked finished with its error and the other jobs go on
-    auto sweep_on = [&](tvs_job* j, hipStream_t st) {
-      try {
-        if (j->dtype == TVS_F32)
-          job_sweep<float>(ctx, j, st);
-        else
-          job_sweep<double>(ctx, j, st);
-      } catch (const Error& e) {
-        if (e.code != TVS_ENONFINITE) throw;
-        j->failed = e.code;
-        j->error = e.what();
-        j->step = 3;
-      }
-    };
-    if (n == 0) return;
-    // The jobs share no device data, so their sweeps may run concurrently:
-    // fork from the caller's stream onto the context's batch streams, deal
-    // the jobs round-robin, and join back (every job's launches stay on one
-    // stream and keep their order, so no result changes).  The batch streams
-    // are also where sweep bodies are recorded as graphs (the caller's
-    // stream may be the legacy default stream, which cannot be captured).
-    const int K = std::min(n, tvs_ctx::kBatchStreams);
-    if (!ctx->bfork) {
+    if (!ctx->bstream) {
+      TVS_HIP(hipStreamCreateWithFlags(&ctx->bstream, hipStreamNonBlocking));
       TVS_HIP(hipEventCreateWithFlags(&ctx->bfork, hipEventDisableTiming));
-      for (int k = 0; k < tvs_ctx::kBatchStreams; ++k) {
-        TVS_HIP(hipStreamCreateWithFlags(&ctx->bstream[k], hipStreamNonBlocking));
-        TVS_HIP(hipEventCreateWithFlags(&ctx->bjoin[k], hipEventDisableTiming));
-      }
+      TVS_HIP(hipEventCreateWithFlags(&ctx->bjoin, hipEventDisableTiming));
     }
+    hipStream_t w = ctx->bstream;
     TVS_HIP(hipEventRecord(ctx->bfork, s));
-    for (int k = 0; k < K; ++k) TVS_HIP(hipStreamWaitEvent(ctx->bstream[k], ctx->bfork, 0));
+    TVS_HIP(hipStreamWaitEvent(w, ctx->bfork, 0));
     auto join = [&] {
-      for (int k = 0; k < K; ++k) {
-        TVS_HIP(hipEventRecord(ctx->bjoin[k], ctx->bstream[k]));
-        TVS_HIP(hipStreamWaitEvent(s, ctx->bjoin[k], 0));
-      }
+      TVS_HIP(hipEventRecord(ctx->bjoin, w));
+      TVS_HIP(hipStreamWaitEvent(s, ctx->bjoin, 0));
     };
     try {
-      for (int i = 0; i < n; ++i) sweep_on(jobs[i], ctx->bstream[i % K]);
+      // 1. heads (and step ends), job by job; a job whose FP64 statistics
+      // come out non-finite fails alone: it is marked finished with its
+      // error and the other jobs go on
+      std::vector<tvs_job*> live;
+      for (int i = 0; i < n; ++i) {
+        tvs_job* j = jobs[i];
+        try {
+          const bool go = j->dtype == TVS_F32 ? job_head<float>(ctx, j, w) : job_head<double>(ctx, j, w);
+          if (go) live.push_back(j);
+        } catch (const Error& e) {
+          if (e.code != TVS_ENONFINITE) throw;
+          j->failed = e.code;
+          j->error = e.what();
+          j->step = 3;
+        }
+      }
+      if (!live.empty()) {
+        // 2. groups of jobs whose inner iterations run as single launches
+        std::vector<BodyGroup> groups;
+        std::map<GroupKey, size_t> gidx;
+        for (tvs_job* j : live) {
+          const GroupKey k = group_key(j);
+          auto it = gidx.find(k);
+          if (it == gidx.end()) {
+            gidx[k] = groups.size();
+            groups.push_back(BodyGroup{j->step, int(j->dtype), {j}, 0});
+          } else {
+            groups[it->second].jobs.push_back(j);
+          }
+        }
+        // their JobBufs tables, uploaded before the bodies run (stream order)
+        std::vector<unsigned char> host;
+        std::vector<unsigned long long> key;
+        for (BodyGroup& G : groups) {
+          G.table_off = host.size();
+          for (tvs_job* j : G.jobs) {
+            const size_t at = host.size();
+            host.resize(at + sizeof(JobBufs<double>));
+            if (G.dtype == TVS_F32) {
+              const JobBufs<float> b = job_bufs<float>(j);
+              std::memcpy(host.data() + at, &b, sizeof b);
+            } else {
+              const JobBufs<double> b = job_bufs<double>(j);
+              std::memcpy(host.data() + at, &b, sizeof b);
+            }
+            key.insert(key.end(), {j->uid, (unsigned long long)j->step,
+                                   (unsigned long long)(G.dtype == TVS_F32 ? job_bufs<float>(j).par
+                                                                           : job_bufs<double>(j).par)});
+          }
+          key.push_back(~0ULL);  // group boundary
+          host.resize((host.size() + 255) / 256 * 256);
+        }
+        static_assert(sizeof(JobBufs<float>) == sizeof(JobBufs<double>), "one table layout");
+        if (ctx->jobtab.bytes < host.size()) {
+          TVS_HIP(hipStreamSynchronize(w));  // earlier launches may still read the old table
+          if (ctx->bgraph) {
+            (void)hipGraphExecDestroy(ctx->bgraph);
+            ctx->bgraph = nullptr;
+            ctx->bkey.clear();
+          }
+          ctx->jobtab.alloc(std::max(host.size(), size_t(1) << 16));
+        }
+        TVS_HIP(hipMemcpyAsync(ctx->jobtab.p, host.data(), host.size(), hipMemcpyHostToDevice, w));
+        // 3. the bodies: replayed from the graph recorded for the same jobs in
+        // the same states, or recorded now (eagerly while kernel timing is on)
+        if (ctx->timer.on) {
+          launch_bodies(ctx, groups, w);
+        } else {
+          if (!(ctx->bgraph && ctx->bkey == key)) {
+            if (ctx->bgraph) {
+              (void)hipGraphExecDestroy(ctx->bgraph);
+              ctx->bgraph = nullptr;
+              ctx->bkey.clear();
+            }
+            hipGraph_t g = nullptr;
+            TVS_HIP(hipStreamBeginCapture(w, hipStreamCaptureModeThreadLocal));
+            try {
+              launch_bodies(ctx, groups, w);
+            } catch (...) {
+              (void)hipStreamEndCapture(w, &g);
+              if (g) (void)hipGraphDestroy(g);
+              throw;
+            }
+            TVS_HIP(hipStreamEndCapture(w, &g));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess)
+              throw Error(TVS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            ctx->bgraph = ex;
+            ctx->bkey = key;
+          }
+          TVS_HIP(hipGraphLaunch(ctx->bgraph, w));
+        }
+        for (const BodyGroup& G : groups)
+          for (tvs_job* j : G.jobs) {
+            if (G.dtype == TVS_F32) job_advance<float>(j);
+            else job_advance<double>(j);
+          }
+        // 4. the ends of the steps whose last sweep this was (each fails
+        // alone on non-finite statistics, as above)
+        for (tvs_job* j : live) {
+          try {
+            if (j->dtype == TVS_F32) job_after<float>(ctx, j, w);
+            else job_after<double>(ctx, j, w);
+          } catch (const Error& e) {
+            if (e.code != TVS_ENONFINITE) throw;
+            j->failed = e.code;
+            j->error = e.what();
+            j->step = 3;
+          }
+        }
+      }
     } catch (...) {
       // whatever was enqueued before the failure stays ordered before the
       // caller's later work
@@ -1663,6 +1874,7 @@ int tvs_job_import_state(tvs_ctx* ctx, const void* buf, size_t bytes, void* stre
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto j = std::make_unique<tvs_job>();
     j->ctx = ctx;
+    j->uid = next_job_uid();
     j->dtype = tvs_dtype(h.dtype);
     j->N2 = h.N2;
     j->N1 = h.N1;

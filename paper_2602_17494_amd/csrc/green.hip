@@ -333,6 +333,14 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   C* buf = reinterpret_cast<C*>(smem_raw);
   int qg, b;
   if (!row_unit(d, qg, b)) return;  // whole workgroup idle
+  C* Sj = d.S;
+  if (d.jobs) {
+    const int j = b / d.nbox_job;
+    const JobBufs<T>& jb = d.jobs[j];
+    u = jb.z[jb.par ^ d.jflip];
+    Sj = jb.S;
+    b -= j * d.nbox_job;
+  }
   const GreenBox bx = d.boxes[b];
   const int Lj = SL ? SL : d.Lj, Lh = SL ? SL / 2 + 1 : d.Lh, ppw = d.ppw;
   const int q0 = qg * ppw;
@@ -359,7 +367,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   else
     res = fft_lds<T, NT>(buf, buf + lds_round(ppw * Lj), d.fj, Lj, ppw, tw, false);
   const int scol = SL ? scol_of(SL) : d.scol;
-  C* S = d.S + static_cast<size_t>(b) * scol * Lh;
+  C* S = Sj + static_cast<size_t>(b) * scol * Lh;
   for (int e = threadIdx.x; e < ppw * Lh; e += NT) {
     const int k = d.fd_ppw.div(e), qq = e - k * ppw;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
@@ -448,19 +456,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C* bufa = reinterpret_cast<C*>(smem_raw);
-  const int b = blockIdx.x;
+  int b = blockIdx.x;
+  C* Sj = d.S;
+  const cplx<T>* specj = d.spec;
+  if (d.jobs) {
+    const int j = b / d.nbox_job;
+    Sj = d.jobs[j].S;
+    specj = d.jobs[j].spec;
+    b -= j * d.nbox_job;
+  }
   const GreenBox bx = d.boxes[b];
   const int Li = SL ? SL : d.Li, Lh = SL ? SL / 2 + 1 : d.Lh, cpw = d.cpw, scol = SL ? scol_of(SL) : d.scol;
   C* bufb = bufa + lds_round(cpw * Li);
   const int k0 = blockIdx.y * cpw;
   const int ncol = min(cpw, Lh - k0);
   const C* tw = stage_twiddles<T, NT, TWL>(bufa + 2 * lds_round(cpw * Li), d.tw_i, Li);
-  C* S = d.S + static_cast<size_t>(b) * scol * Lh + static_cast<size_t>(k0) * scol;
+  C* S = Sj + static_cast<size_t>(b) * scol * Lh + static_cast<size_t>(k0) * scol;
   const size_t slot_sz = static_cast<size_t>(Li) * Lh, col0 = static_cast<size_t>(k0) * Li;
-  const C* s00 = d.spec + static_cast<size_t>(bx.k00) * slot_sz + col0;
-  const C* s01 = d.spec + static_cast<size_t>(bx.k01) * slot_sz + col0;
-  const C* s10 = d.spec + static_cast<size_t>(bx.k10) * slot_sz + col0;
-  const C* s11 = d.spec + static_cast<size_t>(bx.k11) * slot_sz + col0;
+  const C* s00 = specj + static_cast<size_t>(bx.k00) * slot_sz + col0;
+  const C* s01 = specj + static_cast<size_t>(bx.k01) * slot_sz + col0;
+  const C* s10 = specj + static_cast<size_t>(bx.k10) * slot_sz + col0;
+  const C* s11 = specj + static_cast<size_t>(bx.k11) * slot_sz + col0;
   auto ld_s = [&](int c, int r, int) -> C {
     return (c < ncol && r < bx.ni) ? S[c * scol + r] : C{T(0), T(0)};
   };
@@ -537,13 +553,20 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   C* buf = reinterpret_cast<C*>(smem_raw);
   int qg, b;
   if (!row_unit(d, qg, b)) return;  // whole workgroup idle
+  const C* Sj = d.S;
+  if (d.jobs) {
+    const int j = b / d.nbox_job;
+    phi = d.jobs[j].phi;
+    Sj = d.jobs[j].S;
+    b -= j * d.nbox_job;
+  }
   const GreenBox bx = d.boxes[b];
   const int Lj = SL ? SL : d.Lj, Lh = SL ? SL / 2 + 1 : d.Lh, ppw = d.ppw;
   const int q0 = qg * ppw;
   if (2 * q0 >= bx.ni) return;
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
   const int scol = SL ? scol_of(SL) : d.scol;
-  const C* S = d.S + static_cast<size_t>(b) * scol * Lh;
+  const C* S = Sj + static_cast<size_t>(b) * scol * Lh;
   const int half = Lj / 2;
   auto ld = [&](int qq, int k, int) -> C {
     const int ra = 2 * (q0 + qq), rb = ra + 1;
@@ -730,6 +753,9 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
   dev_.scol = scol;
   dev_.ppw = br.batch;
   dev_.nbox = nbox;
+  dev_.nbox_job = nbox;
+  dev_.jobs = nullptr;
+  dev_.jflip = 0;
   dev_.row_groups = ((rows_max + 1) / 2 + br.batch - 1) / br.batch;
   // a workgroup writes (and reads back) 2 ppw rows of every half-spectrum
   // column: below a 128-byte chunk, neighbouring row groups share chunks
@@ -881,6 +907,34 @@ void GreenPlan<T>::apply_div(const T* u, const Frame& uf, T* phi, const Frame& p
     });
     KernelTimer::time(timer, (t + "_rows_inv").c_str(), bytes_rows_inv(), s, [&] {
       hipLaunchKernelGGL(ri, gr, dim3(nt_rows_), lr, s, dev_, phi, pf);
+      TVS_LAUNCH_CHECK();
+    });
+  });
+}
+
+template <typename T>
+void GreenPlan<T>::apply_div_jobs(const JobBufs<T>* jobs, int njobs, int flip, const Frame& uf, const Frame& pf,
+                                  hipStream_t s, KernelTimer* timer, const char* tag) {
+  GreenDev<T> d = dev_;
+  d.jobs = jobs;
+  d.jflip = flip;
+  d.nbox = nbox * njobs;
+  const int row_groups = d.row_groups, nb = d.nbox;
+  const dim3 gr = d.xcd_rows ? dim3(8 * ((row_groups * nb + 7) / 8)) : dim3(row_groups, nb);
+  const dim3 gc(nb, (d.Lh + d.cpw - 1) / d.cpw);
+  const size_t lr = lds_rows(), lc = lds_cols();
+  const std::string t(tag);
+  for_each_variant([&](auto rf, auto cf, auto ri) {
+    KernelTimer::time(timer, (t + "_rows_fwd").c_str(), njobs * bytes_rows_fwd(), s, [&] {
+      hipLaunchKernelGGL(rf, gr, dim3(nt_rows_), lr, s, d, static_cast<const T*>(nullptr), uf);
+      TVS_LAUNCH_CHECK();
+    });
+    KernelTimer::time(timer, (t + "_cols").c_str(), njobs * bytes_cols(), s, [&] {
+      hipLaunchKernelGGL(cf, gc, dim3(nt_cols_), lc, s, d);
+      TVS_LAUNCH_CHECK();
+    });
+    KernelTimer::time(timer, (t + "_rows_inv").c_str(), njobs * bytes_rows_inv(), s, [&] {
+      hipLaunchKernelGGL(ri, gr, dim3(nt_rows_), lr, s, d, static_cast<T*>(nullptr), pf);
       TVS_LAUNCH_CHECK();
     });
   });

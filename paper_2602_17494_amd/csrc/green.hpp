@@ -66,6 +66,38 @@ int green_length(int side);
 bool green_side_ok(int side);
 constexpr int kGreenMaxSide = 5120;
 
+// Buffers of one job in a batched launch.  Jobs of one shape (dtype, image
+// size, layout) share every geometric descriptor (subdomains, theta tables,
+// Green boxes and transform lengths) and differ only in these buffers, so one
+// launch covers the subdomains (or Green boxes) of all of them: frame (or
+// box) z of the launch is frame z mod nsub of job z / nsub.
+//   v[2]   subdomain duals, the two ping-pong states
+//   z[2]   Step 1: vecdiv of v in the same two states
+//   phi    Step 1: the Green boxes' Delta^dagger div z
+//   aux    Step 1: omega frames; Step 2: the b frames
+//   S      Step 1: the local plan's half spectra (work buffer)
+//   spec   Step 1: the local plan's window spectra
+//   par    the state the current sweep's inner iterations started from;
+//          a launch for inner iteration nu reads state par ^ (nu & 1)
+template <typename T>
+struct JobBufs {
+  T* v[2];
+  T* z[2];
+  T* phi;
+  const T* aux;
+  cplx<T>* S;
+  const cplx<T>* spec;
+  int par, pad;
+};
+// A launch's job table: jobs == nullptr for a launch over one problem's own
+// buffers (the pointer arguments); otherwise nsub frames per job and the
+// state flip of this launch.
+template <typename T>
+struct JobRef {
+  const JobBufs<T>* jobs;
+  int nsub, flip;
+};
+
 // Tabulated torus kernel G(u, v), u in [0, n2], v in [0, n1], float64.
 struct GreenTable {
   int n2, n1;
@@ -76,7 +108,10 @@ struct GreenTable {
 
 template <typename T>
 struct GreenDev {
-  int n2, n1, nbox;
+  int n2, n1, nbox;  // nbox: boxes of the launch (all jobs')
+  int nbox_job;      // boxes of one job's plan
+  const JobBufs<T>* jobs;  // batched launch: the jobs' buffers (else nullptr)
+  int jflip;         // batched launch: state flip (input frames z[par ^ jflip])
   int row_groups;  // row-pass workgroups per box (2 ppw rows each)
   int xcd_rows;    // 1: row passes use the XCD-contiguous one-dimensional order
   int Li, Lj, Lh;
@@ -103,6 +138,14 @@ class GreenPlan {
   // support, and div uses the grid's boundary rules (Section 4.1).
   void apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t stream,
                  KernelTimer* timer = nullptr, const char* tag = "green");
+  // The same over njobs jobs of this plan's shape in one launch per pass:
+  // job j's input is its z[par ^ flip] frames (layout uf), its output its
+  // phi frames (layout pf), with its own half spectra S and window spectra
+  // spec (identical geometry, so this plan's descriptors serve all).
+  void apply_div_jobs(const JobBufs<T>* jobs, int njobs, int flip, const Frame& uf, const Frame& pf,
+                      hipStream_t stream, KernelTimer* timer = nullptr, const char* tag = "green");
+  cplx<T>* S_ptr() const { return dev_.S; }
+  const cplx<T>* spec_ptr() const { return dev_.spec; }
   // algorithmic bytes of one launch of each pass (the minimum HBM traffic
   // it must move: its inputs read once, its outputs written once)
   double bytes_rows_fwd() const, bytes_cols() const, bytes_rows_inv() const;

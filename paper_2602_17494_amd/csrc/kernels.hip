@@ -293,9 +293,17 @@ __device__ __forceinline__ bool run_tile(const RunTiles& t, int& q, int& r0, int
 template <typename T>
 __global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, RunTiles rt, Grid g, T inv_h,
                                                         const T* __restrict__ v,
-                                                        T* __restrict__ z) {
+                                                        T* __restrict__ z, JobRef<T> jr) {
   int q, r0, bz;
   if (!run_tile(rt, q, r0, bz)) return;
+  if (jr.jobs) {
+    const int j = bz / jr.nsub;
+    const JobBufs<T>& jb = jr.jobs[j];
+    const int st = jb.par ^ jr.flip;
+    v = jb.v[st];
+    z = jb.z[st];
+    bz -= j * jr.nsub;
+  }
   const SubDesc sd = sf.subs[bz];
   if (r0 >= sd.ai || q >= sd.aj) return;
   const unsigned fp = sf.fp, pl = unsigned(sf.plane);
@@ -325,7 +333,14 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, RunTiles 
 template <typename T>
 void launch_sub_vecdiv(const SubFrames& sf, Grid g, T inv_h, const T* v, T* z, hipStream_t s) {
   const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
-  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, inv_h, v, z);
+  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, inv_h, v, z,
+                     JobRef<T>{nullptr, sf.nsub, 0});
+  TVS_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_sub_vecdiv_jobs(const SubFrames& sf, Grid g, T inv_h, JobRef<T> jr, int njobs, hipStream_t s) {
+  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs);
+  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, inv_h, nullptr, nullptr, jr);
   TVS_LAUNCH_CHECK();
 }
 
@@ -395,9 +410,20 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, RunTiles
                                                          const T* __restrict__ z,
                                                          const T* __restrict__ phi,
                                                          const T* __restrict__ omega,
-                                                         T* __restrict__ v_out) {
+                                                         T* __restrict__ v_out, JobRef<T> jr) {
   int q, r0, bz;
   if (!run_tile(rt, q, r0, bz)) return;
+  if (jr.jobs) {
+    const int j = bz / jr.nsub;
+    const JobBufs<T>& jb = jr.jobs[j];
+    const int st = jb.par ^ jr.flip;
+    v = jb.v[st];
+    z = jb.z[st];
+    phi = jb.phi;
+    omega = jb.aux;
+    v_out = jb.v[st ^ 1];
+    bz -= j * jr.nsub;
+  }
   const SubDesc sd = sf.subs[bz];
   if (r0 >= sd.si || q >= sd.sj) return;
   const unsigned fp = sf.fp, pl = unsigned(sf.plane);
@@ -456,7 +482,16 @@ template <typename T>
 void launch_sub_update1(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* z,
                         const T* phi, const T* omega, T* v_out, hipStream_t s) {
   const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
-  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, z, phi, omega, v_out);
+  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, z, phi, omega, v_out,
+                     JobRef<T>{nullptr, sf.nsub, 0});
+  TVS_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_sub_update1_jobs(const SubFrames& sf, Grid g, StepScalars<T> c, JobRef<T> jr, int njobs,
+                             hipStream_t s) {
+  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs);
+  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, jr);
   TVS_LAUNCH_CHECK();
 }
 
@@ -583,9 +618,18 @@ template <typename T>
 __global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, RunTiles rt, Grid g, StepScalars<T> cs,
                                                          const T* __restrict__ v,
                                                          const T* __restrict__ bfr,
-                                                         T* __restrict__ v_out) {
+                                                         T* __restrict__ v_out, JobRef<T> jr) {
   int q, r0, bz;
   if (!run_tile(rt, q, r0, bz)) return;
+  if (jr.jobs) {
+    const int j = bz / jr.nsub;
+    const JobBufs<T>& jb = jr.jobs[j];
+    const int st = jb.par ^ jr.flip;
+    v = jb.v[st];
+    bfr = jb.aux;
+    v_out = jb.v[st ^ 1];
+    bz -= j * jr.nsub;
+  }
   const SubDesc sd = sf.subs[bz];
   if (r0 >= sd.si || q >= sd.sj) return;
   const unsigned fp = sf.fp, pl = unsigned(sf.plane);
@@ -641,7 +685,16 @@ template <typename T>
 void launch_sub2_update(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* b,
                         T* v_out, hipStream_t s) {
   const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
-  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, b, v_out);
+  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, b, v_out,
+                     JobRef<T>{nullptr, sf.nsub, 0});
+  TVS_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_sub2_update_jobs(const SubFrames& sf, Grid g, StepScalars<T> c, JobRef<T> jr, int njobs,
+                             hipStream_t s) {
+  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs);
+  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, nullptr, nullptr, nullptr,
+                     jr);
   TVS_LAUNCH_CHECK();
 }
 
@@ -839,6 +892,9 @@ void launch_irv1_image(const T* d0, const T* p, const T* xi, Grid g, T inv_h, T 
   template void launch_gap_tfs<T>(const T*, const T*, Grid, T, Partials, double*, hipStream_t); \
   template void launch_sub_theta_p<T>(const SubFrames&, Grid, const T*, int, T*, hipStream_t);  \
   template void launch_sub_vecdiv<T>(const SubFrames&, Grid, T, const T*, T*, hipStream_t);     \
+  template void launch_sub_vecdiv_jobs<T>(const SubFrames&, Grid, T, JobRef<T>, int, hipStream_t); \
+  template void launch_sub_update1_jobs<T>(const SubFrames&, Grid, StepScalars<T>, JobRef<T>, int, hipStream_t); \
+  template void launch_sub2_update_jobs<T>(const SubFrames&, Grid, StepScalars<T>, JobRef<T>, int, hipStream_t); \
   template void launch_sub_omega<T>(const SubFrames&, Grid, T, const T*, const T*, const T*, T*, \
                                     hipStream_t);                                                \
   template void launch_sub_update1<T>(const SubFrames&, Grid, StepScalars<T>, const T*,         \

@@ -78,12 +78,19 @@ template <typename T>
 void launch_sub_theta_p(const SubFrames& sf, Grid g, const T* p, int planes, T* v, hipStream_t s);
 template <typename T>
 void launch_sub_vecdiv(const SubFrames& sf, Grid g, T inv_h, const T* v, T* z, hipStream_t s);
+// batched over jr's jobs: z[state] = vecdiv v[state], state = par ^ flip
+template <typename T>
+void launch_sub_vecdiv_jobs(const SubFrames& sf, Grid g, T inv_h, JobRef<T> jr, int njobs, hipStream_t s);
 template <typename T>
 void launch_sub_omega(const SubFrames& sf, Grid g, T inv_h, const T* r, const T* z, const T* phi,
                       T* omega, hipStream_t s);
 template <typename T>
 void launch_sub_update1(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* z,
                         const T* phi, const T* omega, T* v_out, hipStream_t s);
+// batched: v[state ^ 1] from v[state], z[state], phi, aux (omega)
+template <typename T>
+void launch_sub_update1_jobs(const SubFrames& sf, Grid g, StepScalars<T> c, JobRef<T> jr, int njobs,
+                             hipStream_t s);
 template <typename T>
 void launch_combine(const SubFrames& sf, Grid g, int planes, T ahat, const T* v, T* p, hipStream_t s);
 template <typename T>
@@ -100,6 +107,10 @@ void launch_sub2_prologue(const SubFrames& sf, Grid g, T inv_h, const T* p, cons
 template <typename T>
 void launch_sub2_update(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* b,
                         T* v_out, hipStream_t s);
+// batched: v[state ^ 1] from v[state] and aux (b)
+template <typename T>
+void launch_sub2_update_jobs(const SubFrames& sf, Grid g, StepScalars<T> c, JobRef<T> jr, int njobs,
+                             hipStream_t s);
 template <typename T>
 void launch_energy_rof(const T* p, const T* f2, Grid g, T inv_h, Partials part, double* out,
                        hipStream_t s);
