@@ -580,6 +580,9 @@ def main():
                      "copy_gbs": round(copy_bandwidth(), 1)},
         "kernels": breakdown,
     }
+    t1 = ctx.get_tiles((n, n), torch.float32, lay)
+    out["tiles"] = {"step1_update_run": t1[0], "step1_vecdiv_run": t1[1], "green_rows": t1[2],
+                    "green_cols": t1[3], "step2_update_run": t1[4]}
 
     if not args.no_compare:
         d_f32 = d.double().cpu()

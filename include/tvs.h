@@ -276,6 +276,29 @@ int tvs_energy_history(tvs_ctx* ctx, double* out, int cap, int* n);
 enum { TVS_LP_IMAGE = 0, TVS_LP_BLOCKDCT = 1 };
 int tvs_set_local_projection(tvs_ctx* ctx, int kind);
 
+/* Workgroup shapes (performance only: every choice gives the same results,
+ * bit for bit).  The first time a problem shape (dtype, image size, layout,
+ * h; LP_m realisation) is built in a context, the library times candidate
+ * shapes on the problem's buffers and keeps the fastest for that shape:
+ *   run1, run1d, run2  rows per thread of the Step-1 update, the Step-1
+ *               vecdiv and the Step-2 update kernels (1, 2 or 4)
+ *   rows, cols  targets for the row pairs per row-pass workgroup and the
+ *               columns per column-pass workgroup of the Green passes of
+ *               Step 1's inner iterations (cut to what LDS and thread
+ *               counts allow)
+ *   tvs_set_tiles  force these for the later calls and jobs of the context
+ *                  (0 = the tuner's choice); TVS_EINVAL for a run length not
+ *                  in {0, 1, 2, 4} or rows, cols outside [0, 64].  A rows,
+ *                  cols pair that would move the Green passes to another
+ *                  kernel (another thread count or code path, which may
+ *                  round differently) is not applied: the tuner considers
+ *                  and applies only shapes within the kernels a plan picks
+ *   tvs_get_tiles  the tuner's choice for a shape, out[5] = {run1, run1d,
+ *                  rows, cols, run2} (zeros if not tuned yet); for the block-DCT
+ *                  realisation pass dtype + 2 */
+int tvs_set_tiles(tvs_ctx* ctx, int run1, int run1d, int rows, int cols, int run2);
+int tvs_get_tiles(tvs_ctx* ctx, int N2, int N1, tvs_dtype dtype, const tvs_layout* layout, double h, int* out);
+
 /* Quality measures of Section 5.2 (used to pick the TFS weight delta and the
  * Step-2 parameters in the paper's experiments).
  *   tvs_tangent_field  tau_0 = (-D^{neum-}_y d, D^{neum-}_x d) of an N2 x N1

@@ -63,6 +63,16 @@ template <> constexpr tvs_dtype dtype_of<float>() { return TVS_F32; }
 template <> constexpr tvs_dtype dtype_of<double>() { return TVS_F64; }
 
 using GridKey = std::tuple<int, int, double>;                       // n2, n1, h
+using ShapeKey = std::tuple<int, int, int, double, int, int, int, int>;  // dtype, N2, N1, h, M2, M1, sy, sx
+
+// Workgroup shapes of a problem: the stencil run lengths of Step 1's update
+// and vecdiv and of Step 2's update (1, 2 or 4 rows per thread) and the row
+// pairs / columns per
+// workgroup targets of the Green passes of Step 1's inner iterations
+// (0 = not chosen).  Every choice computes the same values.
+struct Tiles {
+  int run1 = 0, run1d = 0, rows = 0, cols = 0, run2 = 0;
+};
 using ProbKey = std::tuple<int, int, double, int, int, int, int, int>;  // N2, N1, h, M2, M1, sy, sx, LP kind
 
 struct SubSet {
@@ -112,6 +122,8 @@ void finish_subs(SubSet& ss, int fr, int fp) {
   if (4 * 8 * ss.sf.plane >= (1LL << 32)) throw Error(TVS_EINVAL, "layout: subdomain frame too large");
   ss.sf.ay = ss.ay;
   ss.sf.ax = ss.ax;
+  ss.sf.run = 2;
+  ss.sf.run_div = 2;
 }
 
 // the descriptors and theta tables on the device
@@ -237,6 +249,8 @@ struct tvs_ctx {
   std::map<tvs::GridKey, std::unique_ptr<tvs::DevBuf>> projtmp;
   tvs::KernelTimer timer;
   int lp_kind = TVS_LP_IMAGE;  // realisation of LP_m for the one-shot Step-1 calls
+  tvs::Tiles force;            // tvs_set_tiles: fields > 0 override the tuner
+  std::map<tvs::ShapeKey, tvs::Tiles> tuned;  // the tuner's choices per problem shape
   std::vector<double> history;  // energies per sweep of the last one-shot step with statistics
   tvs::DevBuf partials;  // FP64 partial sums
   tvs::DevBuf scal;      // FP64 results (energies per sweep, gap)
@@ -417,6 +431,12 @@ std::unique_ptr<Step2Problem<T>> make_step2(int N2, int N1, double h, const tvs_
   return P;
 }
 
+ShapeKey shape_key(int kind, int N2, int N1, double h, const tvs_layout* l);
+template <typename T>
+void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream_t s);
+template <typename T>
+void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream_t s);
+
 // problems cached in the context by shape (the one-shot calls)
 template <typename T>
 Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
@@ -424,8 +444,8 @@ Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layou
   auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, c->lp_kind};
   auto& mp = s1map<T>(c);
   auto it = mp.find(key);
-  if (it != mp.end()) return *it->second;
-  auto& ref = *(mp[key] = make_step1<T>(c, N2, N1, h, l, s, c->lp_kind));
+  Step1Problem<T>& ref = it != mp.end() ? *it->second : *(mp[key] = make_step1<T>(c, N2, N1, h, l, s, c->lp_kind));
+  apply_tiles1<T>(c, ref, shape_key(int(dtype_of<T>()) + 2 * c->lp_kind, N2, N1, h, l), s);
   return ref;
 }
 
@@ -435,13 +455,187 @@ Step2Problem<T>& get_step2(tvs_ctx* c, int N2, int N1, double h, const tvs_layou
   auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, 0};
   auto& mp = s2map<T>(c);
   auto it = mp.find(key);
-  if (it != mp.end()) return *it->second;
-  auto& ref = *(mp[key] = make_step2<T>(N2, N1, h, l, s));
+  Step2Problem<T>& ref = it != mp.end() ? *it->second : *(mp[key] = make_step2<T>(N2, N1, h, l, s));
+  apply_tiles2<T>(c, ref, shape_key(int(dtype_of<T>()), N2, N1, h, l), s);
   return ref;
 }
 
 Frame global_frame(const Grid& g) { return Frame{0, (long long)g.n2 * g.n1, g.n1}; }
 Frame sub_frame(const SubFrames& sf, int planes) { return Frame{planes * sf.plane, sf.plane, sf.fp}; }
+
+// ---------------------------------------------------------------------------
+// Tuner: the workgroup shapes of a problem, chosen by timing the candidates
+// on the problem's own buffers (zero-filled, before the solve sets them up)
+// the first time a problem shape is built in a context.  The choices are
+// cached per shape; tvs_set_tiles can force them instead.
+// ---------------------------------------------------------------------------
+constexpr int kTuneReps = 8;     // launches per measurement
+constexpr int kTuneTrials = 3;   // measurements per candidate (the fastest counts)
+constexpr float kTuneGain = 0.97f;  // a candidate must beat the current choice by 3 %
+template <typename F>
+float time_launches(hipStream_t s, int reps, F&& f);
+// the fastest of kTuneTrials measurements of kTuneReps launches
+template <typename F>
+float time_best(hipStream_t s, F&& f) {
+  float best = 0;
+  for (int k = 0; k < kTuneTrials; ++k) {
+    const float ms = time_launches(s, kTuneReps, f);
+    if (k == 0 || ms < best) best = ms;
+  }
+  return best;
+}
+template <typename F>
+float time_launches(hipStream_t s, int reps, F&& f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  TVS_HIP(hipEventCreate(&a));
+  TVS_HIP(hipEventCreate(&b));
+  float ms = 0;
+  try {
+    f();  // warm-up
+    TVS_HIP(hipEventRecord(a, s));
+    for (int k = 0; k < reps; ++k) f();
+    TVS_HIP(hipEventRecord(b, s));
+    TVS_HIP(hipEventSynchronize(b));
+    TVS_HIP(hipEventElapsedTime(&ms, a, b));
+  } catch (...) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+constexpr int kTuneRuns[3] = {1, 2, 4};
+constexpr int kTuneRows[4] = {2, 4, 8, 16};
+constexpr int kTuneCols[4] = {1, 2, 3, 4};
+
+template <typename T>
+Tiles tune_step1(Step1Problem<T>& P, hipStream_t s) {
+  Tiles t{};
+  SubFrames& sf = P.ss.sf;
+  const Grid g = P.g;
+  const StepScalars<T> cs{T(0.125), T(1.0 / g.h), T(1), T(1), T(1)};
+  const long long fpl = sf.plane * sf.nsub;
+  launch_fill<T>(dptr<T>(P.va), 4 * fpl, T(0), s);
+  launch_fill<T>(dptr<T>(P.vb), 4 * fpl, T(0), s);
+  launch_fill<T>(dptr<T>(P.za), 2 * fpl, T(0), s);
+  launch_fill<T>(dptr<T>(P.zb), 2 * fpl, T(0), s);
+  launch_fill<T>(dptr<T>(P.phi), fpl, T(0), s);
+  launch_fill<T>(dptr<T>(P.omega), 2 * fpl, T(0), s);
+  // each stencil kernel from the default run length 2, which a candidate
+  // must beat
+  auto pick_run = [&](int& field, auto&& launch) {
+    field = 2;
+    float b = time_best(s, launch);
+    int r = 2;
+    for (int run : kTuneRuns) {
+      if (run == 2) continue;
+      field = run;
+      const float ms = time_best(s, launch);
+      if (ms < kTuneGain * b) {
+        b = ms;
+        r = run;
+      }
+    }
+    field = r;
+    return r;
+  };
+  t.run1 = pick_run(sf.run, [&] {
+    launch_sub_update1<T>(sf, g, cs, dptr<T>(P.va), dptr<T>(P.za), dptr<T>(P.phi), dptr<T>(P.omega),
+                          dptr<T>(P.vb), s);
+  });
+  t.run1d = pick_run(sf.run_div, [&] { launch_sub_vecdiv<T>(sf, g, cs.inv_h, dptr<T>(P.vb), dptr<T>(P.zb), s); });
+  float best = 0;
+  if (!P.bdct) {
+    GreenPlan<T>& gp = P.plain ? *P.global : *P.local;
+    const Frame f2p = sub_frame(sf, 2), f1p = sub_frame(sf, 1);
+    auto apply = [&] { gp.apply_div(dptr<T>(P.za), f2p, dptr<T>(P.phi), f1p, s); };
+    const int cols0 = gp.tile_cols();
+    t.rows = gp.tile_rows();
+    t.cols = cols0;
+    best = time_best(s, apply);
+    const int rows0 = t.rows;
+    for (int rows : kTuneRows) {
+      if (rows == rows0 || !gp.try_tiles(rows, cols0)) continue;
+      const float ms = time_best(s, apply);
+      if (ms < kTuneGain * best) {
+        best = ms;
+        t.rows = rows;
+      }
+      gp.set_tiles(rows0, cols0);
+    }
+    for (int cols : kTuneCols) {
+      if (cols == cols0 || !gp.try_tiles(t.rows, cols)) continue;
+      const float ms = time_best(s, apply);
+      if (ms < kTuneGain * best) {
+        best = ms;
+        t.cols = cols;
+      }
+      gp.set_tiles(t.rows, cols0);
+    }
+    gp.set_tiles(t.rows, t.cols);
+  }
+  return t;
+}
+
+template <typename T>
+int tune_step2(Step2Problem<T>& P, hipStream_t s) {
+  SubFrames& sf = P.ss.sf;
+  const StepScalars<T> cs{T(0.125), T(1.0 / P.g.h), T(1), T(1), T(1)};
+  const long long fpl = sf.plane * sf.nsub;
+  launch_fill<T>(dptr<T>(P.va), 2 * fpl, T(0), s);
+  launch_fill<T>(dptr<T>(P.b), fpl, T(0), s);
+  auto upd = [&] { launch_sub2_update<T>(sf, P.g, cs, dptr<T>(P.va), dptr<T>(P.b), dptr<T>(P.vb), s); };
+  int pick = 2;
+  sf.run = 2;
+  float best = time_best(s, upd);
+  for (int run : kTuneRuns) {
+    if (run == 2) continue;
+    sf.run = run;
+    const float ms = time_best(s, upd);
+    if (ms < kTuneGain * best) {
+      best = ms;
+      pick = run;
+    }
+  }
+  sf.run = pick;
+  return pick;
+}
+
+// kind: the dtype, plus 2 for a Step-1 problem with the block-DCT LP_m
+ShapeKey shape_key(int kind, int N2, int N1, double h, const tvs_layout* l) {
+  return ShapeKey{kind, N2, N1, h, l->M2, l->M1, l->s_y, l->s_x};
+}
+
+// The workgroup shapes of a Step-1 problem: forced, cached for its shape, or
+// tuned now (and cached).
+template <typename T>
+void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream_t s) {
+  Tiles& cached = c->tuned[key];
+  if (cached.run1 == 0) {
+    const Tiles t = tune_step1<T>(P, s);
+    cached.run1 = t.run1;
+    cached.run1d = t.run1d;
+    cached.rows = t.rows;
+    cached.cols = t.cols;
+  }
+  const Tiles& f = c->force;
+  P.ss.sf.run = f.run1 > 0 ? f.run1 : cached.run1;
+  P.ss.sf.run_div = f.run1d > 0 ? f.run1d : cached.run1d;
+  if (!P.bdct) {
+    GreenPlan<T>& gp = P.plain ? *P.global : *P.local;
+    const int rows = f.rows > 0 ? f.rows : cached.rows, cols = f.cols > 0 ? f.cols : cached.cols;
+    if (rows > 0 && cols > 0 && (rows != gp.tile_rows() || cols != gp.tile_cols())) gp.try_tiles(rows, cols);
+  }
+}
+template <typename T>
+void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream_t s) {
+  Tiles& cached = c->tuned[key];
+  if (cached.run2 == 0) cached.run2 = tune_step2<T>(P, s);
+  P.ss.sf.run = c->force.run2 > 0 ? c->force.run2 : cached.run2;
+}
 
 struct Host64 {
   std::vector<double> v;
@@ -957,6 +1151,9 @@ void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s,
   st->e2.alloc(sizeof(double) * (size_t(j->its.sweeps) + 3));
   st->p1 = make_step1<T>(c, N2, N1, j->prm.h, &j->lay, s, TVS_LP_IMAGE, false);
   st->p2 = make_step2<T>(N2, N1, j->prm.h, &j->lay, s);
+  const ShapeKey sk = shape_key(int(dtype_of<T>()), N2, N1, j->prm.h, &j->lay);
+  apply_tiles1<T>(c, *st->p1, sk, s);
+  apply_tiles2<T>(c, *st->p2, sk, s);
   TVS_HIP(hipMemcpyAsync(st->d0.p, d0, esz * size_t(N2) * N1, kind, s));
   st->r1 = std::make_unique<Step1Run<T>>(*st->p1, st->d0.template as<T>(), N2, N1, &j->prm, &j->lay, &j->its,
                                          Partials{st->part.template as<double>(), 1024}, st->e1.template as<double>(), &c->timer);
@@ -1522,6 +1719,31 @@ int tvs_energy_history(tvs_ctx* ctx, double* out, int cap, int* n) {
     if (cap < 0 || (cap > 0 && !out)) throw Error(TVS_EINVAL, "bad output buffer");
     *n = static_cast<int>(ctx->history.size());
     for (int k = 0; k < std::min(cap, *n); ++k) out[k] = ctx->history[k];
+  });
+}
+
+int tvs_set_tiles(tvs_ctx* ctx, int run1, int run1d, int rows, int cols, int run2) {
+  return guarded([&] {
+    if (!ctx) throw Error(TVS_EINVAL, "NULL context");
+    auto run_ok = [](int r) { return r == 0 || r == 1 || r == 2 || r == 4; };
+    if (!run_ok(run1) || !run_ok(run1d) || !run_ok(run2))
+      throw Error(TVS_EINVAL, "tiles: run lengths must be 0, 1, 2 or 4");
+    if (rows < 0 || rows > 64 || cols < 0 || cols > 64) throw Error(TVS_EINVAL, "tiles: rows and cols must lie in [0, 64]");
+    ctx->force = Tiles{run1, run1d, rows, cols, run2};
+  });
+}
+
+int tvs_get_tiles(tvs_ctx* ctx, int N2, int N1, tvs_dtype dtype, const tvs_layout* layout, double h, int* out) {
+  return guarded([&] {
+    if (!ctx || !layout || !out) throw Error(TVS_EINVAL, "NULL argument");
+    if (dtype != TVS_F32 && dtype != TVS_F64) throw Error(TVS_EINVAL, "unknown dtype");
+    auto it = ctx->tuned.find(shape_key(int(dtype), N2, N1, h, layout));
+    const Tiles t = it == ctx->tuned.end() ? Tiles{} : it->second;
+    out[0] = t.run1;
+    out[1] = t.run1d;
+    out[2] = t.rows;
+    out[3] = t.cols;
+    out[4] = t.run2;
   });
 }
 

@@ -325,7 +325,7 @@ constexpr int scol_of(int sl) { return sl == 512 ? 272 : sl == 576 ? 304 : 368; 
 // SL = 512, 576 or 648: the transform length is fixed at compile time
 // (FftOf<SL>), else 0.  OB: one LDS buffer (long transforms, 1024 threads,
 // global twiddles).
-template <typename T, int NT, bool TWL, int SL, bool OB>
+template <typename T, int NT, bool TWL, int SL, bool OB, bool JB>
 __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* __restrict__ u,
                                                        Frame uf) {
   using C = cplx<T>;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   int qg, b;
   if (!row_unit(d, qg, b)) return;  // whole workgroup idle
   C* Sj = d.S;
-  if (d.jobs) {
+  if constexpr (JB) {
     const int j = b / d.nbox_job;
     const JobBufs<T>& jb = d.jobs[j];
     u = jb.z[jb.par ^ d.jflip];
@@ -451,7 +451,7 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
 // tile of neighbouring boxes; boxes of one subdomain column then share an
 // XCD and its L2 for the window spectra they have in common.
 // (at most 128 VGPRs, so that four 256-thread workgroups fit on a CU)
-template <typename T, int NT, bool TWL, int SL, bool OB>
+template <typename T, int NT, bool TWL, int SL, bool OB, bool JB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_green_cols(GreenDev<T> d) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   int b = blockIdx.x;
   C* Sj = d.S;
   const cplx<T>* specj = d.spec;
-  if (d.jobs) {
+  if constexpr (JB) {
     const int j = b / d.nbox_job;
     Sj = d.jobs[j].S;
     specj = d.jobs[j].spec;
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
 }
 
-template <typename T, int NT, bool TWL, int SL, bool OB>
+template <typename T, int NT, bool TWL, int SL, bool OB, bool JB>
 __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restrict__ phi, Frame pf) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
   int qg, b;
   if (!row_unit(d, qg, b)) return;  // whole workgroup idle
   const C* Sj = d.S;
-  if (d.jobs) {
+  if constexpr (JB) {
     const int j = b / d.nbox_job;
     phi = d.jobs[j].phi;
     Sj = d.jobs[j].S;
@@ -731,54 +731,100 @@ GreenPlan<T>::GreenPlan(const GreenTable& table, const std::vector<std::array<in
     TVS_HIP(hipStreamSynchronize(s));
   }
 
-  // 8 row pairs (16 rows) per workgroup give 128-byte chunks of float32 half
-  // spectra in the transposed layout; the column pass, which is bound by
-  // its barriers rather than by HBM, keeps 256-thread workgroups
-  Batch br = pick_batch<T>(Lj, 8, 80 * 1024);
-  Batch bc = pick_batch<T>(Li, std::max(1, (kFftThreads * FftCap<T, kFftThreads>::elems) / Li), 80 * 1024);
-  // a transform too long for two LDS buffers puts all three passes on the
-  // one-buffer engine (one kernel variant for long plans)
-  ob_ = br.ob || bc.ob;
-  if (ob_) {
-    br = pick_batch_1b<T>(Lj, br.ob ? br.batch : 8);
-    bc = pick_batch_1b<T>(Li, 1);
-  }
-  nt_rows_ = br.nt;
-  nt_cols_ = bc.nt;
+  fi_ = fi;
+  fj_ = fj;
   dev_.n2 = n2;
   dev_.n1 = n1;
   dev_.Li = Li;
   dev_.Lj = Lj;
   dev_.Lh = Lh;
   dev_.scol = scol;
-  dev_.ppw = br.batch;
   dev_.nbox = nbox;
   dev_.nbox_job = nbox;
   dev_.jobs = nullptr;
   dev_.jflip = 0;
-  dev_.row_groups = ((rows_max + 1) / 2 + br.batch - 1) / br.batch;
-  // a workgroup writes (and reads back) 2 ppw rows of every half-spectrum
-  // column: below a 128-byte chunk, neighbouring row groups share chunks
-  dev_.xcd_rows = 2 * br.batch * int(sizeof(cplx<T>)) < 128 ? 1 : 0;
-  dev_.cpw = bc.batch;
   dev_.fd_Li = make_fastdiv(Li);
   dev_.fd_Lj = make_fastdiv(Lj);
-  dev_.fd_ppw = make_fastdiv(br.batch);
   dev_.inv_h = T(1) / T(table.h);
   dev_.boxes = boxes_d_.as<GreenBox>();
   dev_.tw_i = tw_i_.as<cplx<T>>();
   dev_.tw_j = tw_j_.as<cplx<T>>();
   dev_.S = S_.as<cplx<T>>();
   dev_.spec = spec_.as<cplx<T>>();
-  dev_.fi = ob_ ? make_fft_desc(Li, kLongRadix<T>) : fi;
-  dev_.fj = ob_ ? make_fft_desc(Lj, kLongRadix<T>) : fj;
+  // 8 row pairs (16 rows) per workgroup give 128-byte chunks of float32 half
+  // spectra in the transposed layout; the column pass, which is bound by
+  // its barriers rather than by HBM, keeps 256-thread workgroups
+  set_tiles(kDefaultTileRows, (kFftThreads * FftCap<T, kFftThreads>::elems) / Li);
+}
+
+// The kernel code path a plan's launches take: the one-buffer engine, the
+// workgroup sizes, the twiddle placement, compile-time or runtime transform
+// lengths, and (float) whether the column pass loads its window spectra
+// ahead.  Workgroup shapes that keep it compute the same values bit for bit;
+// another path may round differently (the compiler contracts differently).
+template <typename T>
+std::array<int, 7> GreenPlan<T>::variant() const {
+  int sl = 0;
+  for_each_variant([&](auto, auto cf, auto) {
+    sl = (reinterpret_cast<const void*>(cf) == reinterpret_cast<const void*>(
+                                                   k_green_cols<T, kFftThreads, true, 512, false, false>) ||
+          reinterpret_cast<const void*>(cf) == reinterpret_cast<const void*>(
+                                                   k_green_cols<T, kFftThreads, true, 576, false, false>) ||
+          reinterpret_cast<const void*>(cf) == reinterpret_cast<const void*>(
+                                                   k_green_cols<T, kFftThreads, true, 648, false, false>))
+             ? 1
+             : 0;
+  });
+  const int pre = sizeof(T) == 4 && !ob_ && dev_.fi.npass >= 2 && dev_.fi.nbf[0].d * dev_.cpw <= nt_cols_;
+  return {ob_ ? 1 : 0, nt_rows_, nt_cols_, twl_rows_ ? 1 : 0, twl_cols_ ? 1 : 0, sl, sl ? 1 : pre};
+}
+
+template <typename T>
+bool GreenPlan<T>::try_tiles(int rows, int cols) {
+  const int r0 = tile_rows_, c0 = tile_cols_;
+  const std::array<int, 7> v0 = variant();
+  set_tiles(rows, cols);
+  if (variant() == v0) return true;
+  set_tiles(r0, c0);
+  return false;
+}
+
+template <typename T>
+void GreenPlan<T>::set_tiles(int rows, int cols) {
+  rows = std::max(1, rows);
+  cols = std::max(1, cols);
+  Batch br = pick_batch<T>(Lj, rows, 80 * 1024);
+  Batch bc = pick_batch<T>(Li, cols, 80 * 1024);
+  // a transform too long for two LDS buffers puts all three passes on the
+  // one-buffer engine (one kernel variant for long plans)
+  ob_ = br.ob || bc.ob;
+  if (ob_) {
+    br = pick_batch_1b<T>(Lj, br.ob ? br.batch : rows);
+    bc = pick_batch_1b<T>(Li, 1);
+  }
+  tile_rows_ = rows;
+  tile_cols_ = cols;
+  nt_rows_ = br.nt;
+  nt_cols_ = bc.nt;
+  dev_.ppw = br.batch;
+  dev_.row_groups = ((rows_max + 1) / 2 + br.batch - 1) / br.batch;
+  // a workgroup writes (and reads back) 2 ppw rows of every half-spectrum
+  // column: below a 128-byte chunk, neighbouring row groups share chunks
+  dev_.xcd_rows = 2 * br.batch * int(sizeof(cplx<T>)) < 128 ? 1 : 0;
+  dev_.cpw = bc.batch;
+  dev_.fd_ppw = make_fastdiv(br.batch);
+  dev_.fi = ob_ ? make_fft_desc(Li, kLongRadix<T>) : fi_;
+  dev_.fj = ob_ ? make_fft_desc(Lj, kLongRadix<T>) : fj_;
   twl_rows_ = !ob_ && Lj * sizeof(cplx<T>) <= 16 * 1024;
   twl_cols_ = !ob_ && Li * sizeof(cplx<T>) <= 16 * 1024;
-  for_each_variant([&](auto rf, auto cf, auto ri) {
-    allow_lds(rf, lds_rows());
-    allow_lds(ri, lds_rows());
-    allow_lds(cf, lds_cols());
-  });
+  for (bool jobs : {false, true})
+    for_each_variant(
+        [&](auto rf, auto cf, auto ri) {
+          allow_lds(rf, lds_rows());
+          allow_lds(ri, lds_rows());
+          allow_lds(cf, lds_cols());
+        },
+        jobs);
 }
 
 template <typename T>
@@ -794,15 +840,25 @@ size_t GreenPlan<T>::lds_cols() const {
 // launches (workgroup size and twiddle placement of each pass).
 template <typename T>
 template <typename F>
-void GreenPlan<T>::for_each_variant(F&& f) const {
+void GreenPlan<T>::for_each_variant(F&& f, bool jobs) const {
   auto pick = [&](auto nt_r, auto nt_c, auto twr, auto twc, auto sl) {
-    f(k_green_rows_fwd<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value, false>,
-      k_green_cols<T, decltype(nt_c)::value, decltype(twc)::value, decltype(sl)::value, false>,
-      k_green_rows_inv<T, decltype(nt_r)::value, decltype(twr)::value, decltype(sl)::value, false>);
+    constexpr int R = decltype(nt_r)::value, Cn = decltype(nt_c)::value, SL = decltype(sl)::value;
+    constexpr bool TR = decltype(twr)::value, TC = decltype(twc)::value;
+    if (jobs)
+      f(k_green_rows_fwd<T, R, TR, SL, false, true>, k_green_cols<T, Cn, TC, SL, false, true>,
+        k_green_rows_inv<T, R, TR, SL, false, true>);
+    else
+      f(k_green_rows_fwd<T, R, TR, SL, false, false>, k_green_cols<T, Cn, TC, SL, false, false>,
+        k_green_rows_inv<T, R, TR, SL, false, false>);
   };
   if (ob_) {
-    f(k_green_rows_fwd<T, kFftThreadsLong, false, 0, true>, k_green_cols<T, kFftThreadsLong, false, 0, true>,
-      k_green_rows_inv<T, kFftThreadsLong, false, 0, true>);
+    if (jobs)
+      f(k_green_rows_fwd<T, kFftThreadsLong, false, 0, true, true>, k_green_cols<T, kFftThreadsLong, false, 0, true, true>,
+        k_green_rows_inv<T, kFftThreadsLong, false, 0, true, true>);
+    else
+      f(k_green_rows_fwd<T, kFftThreadsLong, false, 0, true, false>,
+        k_green_cols<T, kFftThreadsLong, false, 0, true, false>,
+        k_green_rows_inv<T, kFftThreadsLong, false, 0, true, false>);
     return;
   }
   using S = std::integral_constant<int, kFftThreads>;
@@ -937,7 +993,7 @@ void GreenPlan<T>::apply_div_jobs(const JobBufs<T>* jobs, int njobs, int flip, c
       hipLaunchKernelGGL(ri, gr, dim3(nt_rows_), lr, s, d, static_cast<T*>(nullptr), pf);
       TVS_LAUNCH_CHECK();
     });
-  });
+  }, true);
 }
 
 template class GreenPlan<float>;

@@ -98,6 +98,8 @@ struct JobRef {
   int nsub, flip;
 };
 
+constexpr int kDefaultTileRows = 8;
+
 // Tabulated torus kernel G(u, v), u in [0, n2], v in [0, n1], float64.
 struct GreenTable {
   int n2, n1;
@@ -145,6 +147,17 @@ class GreenPlan {
   void apply_div_jobs(const JobBufs<T>* jobs, int njobs, int flip, const Frame& uf, const Frame& pf,
                       hipStream_t stream, KernelTimer* timer = nullptr, const char* tag = "green");
   cplx<T>* S_ptr() const { return dev_.S; }
+  // Workgroup shape of the passes: about `rows` row pairs per row-pass
+  // workgroup and `cols` columns per column-pass workgroup (targets, cut to
+  // what the LDS and the thread counts allow).  Every shape computes the
+  // same values; only the speed differs.
+  void set_tiles(int rows, int cols);
+  // set_tiles if the kernels keep their code path (so the results keep their
+  // bits); otherwise the shape in force stays and the call returns false
+  bool try_tiles(int rows, int cols);
+  std::array<int, 7> variant() const;
+  int tile_rows() const { return tile_rows_; }
+  int tile_cols() const { return tile_cols_; }
   const cplx<T>* spec_ptr() const { return dev_.spec; }
   // algorithmic bytes of one launch of each pass (the minimum HBM traffic
   // it must move: its inputs read once, its outputs written once)
@@ -162,8 +175,10 @@ class GreenPlan {
   int nt_rows_ = 0, nt_cols_ = 0;
   bool twl_rows_ = false, twl_cols_ = false;  // twiddle tables staged in LDS
   bool ob_ = false;  // transforms on the one-buffer LDS engine (long lengths)
+  int tile_rows_ = 0, tile_cols_ = 0;  // set_tiles targets in force
+  FftDesc fi_{}, fj_{};  // descriptors of the transform lengths
   size_t lds_rows() const, lds_cols() const;
-  template <typename F> void for_each_variant(F&& f) const;
+  template <typename F> void for_each_variant(F&& f, bool jobs = false) const;
   double sum_ni_lh_ = 0, sum_box_px_ = 0;
   DevBuf boxes_d_, tw_i_, tw_j_, spec_, S_;
 };

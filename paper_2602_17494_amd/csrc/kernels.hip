@@ -9,6 +9,8 @@
 // the subdomain's first point; everything outside a frame's support is 0.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace tvs {
 
 constexpr int kBX = 64, kBY = 4;  // 2-D block shape (one wavefront per row)
@@ -253,24 +255,34 @@ __device__ __forceinline__ void st32(T* base, unsigned e, T x) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * unsigned(sizeof(T))) = x;
 }
 
-// Per-subdomain stencil kernels give each thread a run of kRunY consecutive
+// Per-subdomain stencil kernels give each thread a run of RY consecutive
 // rows of one frame column (a 64-wide wavefront spans one row segment, so
-// row quantities are uniform over it).
-constexpr int kRunY = 2;
+// row quantities are uniform over it).  RY is 1, 2 or 4, chosen per problem
+// shape by the tuner (SubFrames::run); every choice computes the same
+// values.
 
-// Tiles of kBX columns x kBY * kRunY rows of the nz frames are numbered rows
+// Tiles of kBX columns x kBY * RY rows of the nz frames are numbered rows
 // fastest, then columns, then frames.  Workgroups are dealt round-robin to
 // the 8 XCDs, so workgroup w takes tile (w mod 8) * per + w / 8 (per = tiles
 // per XCD, the grid is 8 * per): each XCD then works through a contiguous
 // range of tiles, and tiles that share halo rows run on the same XCD, close
 // in time, and find those rows in its L2.
 struct RunTiles {
-  int ncx, nry, n;
+  int ncx, nry, n, ry;
 };
-static RunTiles run_tiles(int n2, int n1, int nz) {
-  RunTiles t{(n1 + kBX - 1) / kBX, (n2 + kBY * kRunY - 1) / (kBY * kRunY), 0};
+static RunTiles run_tiles(int n2, int n1, int nz, int ry) {
+  RunTiles t{(n1 + kBX - 1) / kBX, (n2 + kBY * ry - 1) / (kBY * ry), 0, ry};
   t.n = t.ncx * t.nry * nz;
   return t;
+}
+// calls f(std::integral_constant<int, RY>{}) for the run length of sf
+template <typename F>
+static void with_run(int run, F&& f) {
+  switch (run) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    default: f(std::integral_constant<int, 2>{}); break;
+  }
 }
 static dim3 grid_runs(const RunTiles& t) { return dim3(8 * ((t.n + 7) / 8)); }
 // This thread's frame column q, first row r0 (wavefront-uniform) and frame;
@@ -283,20 +295,20 @@ __device__ __forceinline__ bool run_tile(const RunTiles& t, int& q, int& r0, int
   const int ry = tile % t.nry, rest = tile / t.nry;
   box = rest / t.ncx;
   q = (rest - box * t.ncx) * kBX + threadIdx.x;
-  r0 = __builtin_amdgcn_readfirstlane((ry * kBY + int(threadIdx.y)) * kRunY);
+  r0 = __builtin_amdgcn_readfirstlane((ry * kBY + int(threadIdx.y)) * t.ry);
   return true;
 }
 
 // z = vecdiv(E_m v) on the grown subdomain.  Only the grown subdomain is
 // written: the rest of a z frame is 0 from the start of the solve.  Row runs
 // as in the update kernels below, carrying v_xy and v_yy of the row above.
-template <typename T>
+template <typename T, int RY, bool JB>
 __global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, RunTiles rt, Grid g, T inv_h,
                                                         const T* __restrict__ v,
                                                         T* __restrict__ z, JobRef<T> jr) {
   int q, r0, bz;
   if (!run_tile(rt, q, r0, bz)) return;
-  if (jr.jobs) {
+  if constexpr (JB) {
     const int j = bz / jr.nsub;
     const JobBufs<T>& jb = jr.jobs[j];
     const int st = jb.par ^ jr.flip;
@@ -318,7 +330,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, RunTiles 
   const unsigned dl = q > 0 ? 1u : 0u;
   unsigned o = unsigned(r0) * fp + unsigned(q);
   T u1 = r0 > 0 ? ld32(v1, o - fp) : T(0), u3 = r0 > 0 ? ld32(v3, o - fp) : T(0);
-  const int rend = min(kRunY, sd.ai - r0);
+  const int rend = min(RY, sd.ai - r0);
   int gi = sd.i0 + r0;
   for (int rr = 0; rr < rend; ++rr, o += fp, ++gi) {
     const bool lasty = gi == g.n2 - 1;
@@ -332,16 +344,21 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_vecdiv(SubFrames sf, RunTiles 
 }
 template <typename T>
 void launch_sub_vecdiv(const SubFrames& sf, Grid g, T inv_h, const T* v, T* z, hipStream_t s) {
-  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
-  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, inv_h, v, z,
-                     JobRef<T>{nullptr, sf.nsub, 0});
-  TVS_LAUNCH_CHECK();
+  with_run(sf.run_div, [&](auto ry) {
+    const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub, ry);
+    hipLaunchKernelGGL((k_sub_vecdiv<T, decltype(ry)::value, false>), grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g,
+                       inv_h, v, z, JobRef<T>{nullptr, sf.nsub, 0});
+    TVS_LAUNCH_CHECK();
+  });
 }
 template <typename T>
 void launch_sub_vecdiv_jobs(const SubFrames& sf, Grid g, T inv_h, JobRef<T> jr, int njobs, hipStream_t s) {
-  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs);
-  hipLaunchKernelGGL(k_sub_vecdiv<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, inv_h, nullptr, nullptr, jr);
-  TVS_LAUNCH_CHECK();
+  with_run(sf.run_div, [&](auto ry) {
+    const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs, ry);
+    hipLaunchKernelGGL((k_sub_vecdiv<T, decltype(ry)::value, true>), grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g,
+                       inv_h, nullptr, nullptr, jr);
+    TVS_LAUNCH_CHECK();
+  });
 }
 
 // (grad phi)_c inside a frame, with the grid's last-row/column rule
@@ -398,13 +415,13 @@ __device__ __forceinline__ double dual_scale(double th, double t, double nn) {
 // Inner iteration of Algorithm 5:
 //   y = LP_m(z) = z - grad phi,  psi_k = grad(y_k - omega_k) on the subdomain,
 //   v_k <- theta (v_k + t psi_k) / (theta + t |psi_k|).
-// Each thread walks kRunY consecutive rows of one column; w_k = y_k - omega_k
+// Each thread walks RY consecutive rows of one column; w_k = y_k - omega_k
 // at (r + 1, q), needed for psi at row r, is carried to the next row.  The
 // wavefront spans one row segment (kBX == 64), so row quantities are uniform.
 // Neighbour offsets are clamped to 0 where the grid ends, which makes the
 // corresponding forward difference of phi vanish and keeps every load inside
 // the frame; psi components there are set to 0 explicitly.
-template <typename T>
+template <typename T, int RY, bool JB>
 __global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, RunTiles rt, Grid g, StepScalars<T> cs,
                                                          const T* __restrict__ v,
                                                          const T* __restrict__ z,
@@ -413,7 +430,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, RunTiles
                                                          T* __restrict__ v_out, JobRef<T> jr) {
   int q, r0, bz;
   if (!run_tile(rt, q, r0, bz)) return;
-  if (jr.jobs) {
+  if constexpr (JB) {
     const int j = bz / jr.nsub;
     const JobBufs<T>& jb = jr.jobs[j];
     const int st = jb.par ^ jr.flip;
@@ -453,7 +470,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, RunTiles
   int gi = sd.i0 + r0;
   T wa0 = ld32(z0, o) - (ld32(ph, o + dx) - ld32(ph, o)) * ih - ld32(m0, o);
   T wa1 = ld32(z1, o) - (ld32(ph, o + (gi == g.n2 - 1 ? 0u : fp)) - ld32(ph, o)) * ih - ld32(m1, o);
-  const int rend = min(kRunY, sd.si - r0);
+  const int rend = min(RY, sd.si - r0);
   for (int rr = 0; rr < rend; ++rr, o += fp, ++gi) {
     const bool lasty = gi == g.n2 - 1;                  // uniform over the wavefront
     const unsigned dy = lasty ? 0u : fp;                // (grad phi)_y in row r; lower neighbour
@@ -481,18 +498,22 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub_update1(SubFrames sf, RunTiles
 template <typename T>
 void launch_sub_update1(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* z,
                         const T* phi, const T* omega, T* v_out, hipStream_t s) {
-  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
-  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, z, phi, omega, v_out,
-                     JobRef<T>{nullptr, sf.nsub, 0});
-  TVS_LAUNCH_CHECK();
+  with_run(sf.run, [&](auto ry) {
+    const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub, ry);
+    hipLaunchKernelGGL((k_sub_update1<T, decltype(ry)::value, false>), grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c,
+                       v, z, phi, omega, v_out, JobRef<T>{nullptr, sf.nsub, 0});
+    TVS_LAUNCH_CHECK();
+  });
 }
 template <typename T>
 void launch_sub_update1_jobs(const SubFrames& sf, Grid g, StepScalars<T> c, JobRef<T> jr, int njobs,
                              hipStream_t s) {
-  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs);
-  hipLaunchKernelGGL(k_sub_update1<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, nullptr, nullptr, nullptr,
-                     nullptr, nullptr, jr);
-  TVS_LAUNCH_CHECK();
+  with_run(sf.run, [&](auto ry) {
+    const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs, ry);
+    hipLaunchKernelGGL((k_sub_update1<T, decltype(ry)::value, true>), grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, jr);
+    TVS_LAUNCH_CHECK();
+  });
 }
 
 // p^{n+1} = (1 - ahat) p^n + ahat sum_m E_m v_m (Algorithm 2).  Along each
@@ -614,14 +635,14 @@ void launch_sub2_prologue(const SubFrames& sf, Grid g, T inv_h, const T* p, cons
 // the next row.  Terms of the backward differences that fall outside the
 // frame support, or on the grid's last row/column, are selected to 0; their
 // loads use clamped offsets inside the frame.
-template <typename T>
+template <typename T, int RY, bool JB>
 __global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, RunTiles rt, Grid g, StepScalars<T> cs,
                                                          const T* __restrict__ v,
                                                          const T* __restrict__ bfr,
                                                          T* __restrict__ v_out, JobRef<T> jr) {
   int q, r0, bz;
   if (!run_tile(rt, q, r0, bz)) return;
-  if (jr.jobs) {
+  if constexpr (JB) {
     const int j = bz / jr.nsub;
     const JobBufs<T>& jb = jr.jobs[j];
     const int st = jb.par ^ jr.flip;
@@ -654,7 +675,7 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, RunTiles
   T yu = r0 > 0 ? ld32(vy, o - fp) : T(0);
   const T xl0 = q > 0 ? ld32(vx, o - dl) : T(0);
   T sa = (((lastx ? T(0) : xa) - xl0) + ((gi == g.n2 - 1 ? T(0) : ya) - yu)) * ih + ld32(bb, o);
-  const int rend = min(kRunY, sd.si - r0);
+  const int rend = min(RY, sd.si - r0);
   for (int rr = 0; rr < rend; ++rr, o += fp, ++gi) {
     const int r = r0 + rr;
     const bool lasty = gi == g.n2 - 1;
@@ -684,18 +705,22 @@ __global__ __launch_bounds__(kBX* kBY) void k_sub2_update(SubFrames sf, RunTiles
 template <typename T>
 void launch_sub2_update(const SubFrames& sf, Grid g, StepScalars<T> c, const T* v, const T* b,
                         T* v_out, hipStream_t s) {
-  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub);
-  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, v, b, v_out,
-                     JobRef<T>{nullptr, sf.nsub, 0});
-  TVS_LAUNCH_CHECK();
+  with_run(sf.run, [&](auto ry) {
+    const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub, ry);
+    hipLaunchKernelGGL((k_sub2_update<T, decltype(ry)::value, false>), grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c,
+                       v, b, v_out, JobRef<T>{nullptr, sf.nsub, 0});
+    TVS_LAUNCH_CHECK();
+  });
 }
 template <typename T>
 void launch_sub2_update_jobs(const SubFrames& sf, Grid g, StepScalars<T> c, JobRef<T> jr, int njobs,
                              hipStream_t s) {
-  const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs);
-  hipLaunchKernelGGL(k_sub2_update<T>, grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c, nullptr, nullptr, nullptr,
-                     jr);
-  TVS_LAUNCH_CHECK();
+  with_run(sf.run, [&](auto ry) {
+    const RunTiles rt = run_tiles(sf.fr, sf.fp, sf.nsub * njobs, ry);
+    hipLaunchKernelGGL((k_sub2_update<T, decltype(ry)::value, true>), grid_runs(rt), dim3(kBX, kBY), 0, s, sf, rt, g, c,
+                       nullptr, nullptr, nullptr, jr);
+    TVS_LAUNCH_CHECK();
+  });
 }
 
 template <typename T>

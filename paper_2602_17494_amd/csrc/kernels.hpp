@@ -67,6 +67,8 @@ struct SubFrames {
   const float* thx_f;
   const double* thy_d;
   const double* thx_d;
+  int run;                    // rows per thread of the update kernels (1, 2 or 4)
+  int run_div;                // rows per thread of the Step-1 vecdiv kernel
 };
 template <typename T> __device__ __forceinline__ const T* theta_rows(const SubFrames& sf);
 template <> __device__ __forceinline__ const float* theta_rows<float>(const SubFrames& sf) { return sf.thy_f; }

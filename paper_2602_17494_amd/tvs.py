@@ -115,6 +115,10 @@ def load():
     lib.tvs_tangent_field.restype = ci
     lib.tvs_quality.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd), vp]
     lib.tvs_quality.restype = ci
+    lib.tvs_set_tiles.argtypes = [vp, ci, ci, ci, ci, ci]
+    lib.tvs_set_tiles.restype = ci
+    lib.tvs_get_tiles.argtypes = [vp, ci, ci, ci, L, cd, ctypes.POINTER(ci)]
+    lib.tvs_get_tiles.restype = ci
     lib.tvs_quality_noalloc.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd), vp]
     lib.tvs_quality_noalloc.restype = ci
     lib.tvs_job_destroy.argtypes = [vp]
@@ -129,6 +133,7 @@ EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_byte
             "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
             "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state",
             "tvs_tangent_field", "tvs_quality", "tvs_quality_noalloc", "tvs_set_local_projection",
+            "tvs_set_tiles", "tvs_get_tiles",
             "tvs_energy_history"]
 
 
@@ -326,6 +331,19 @@ class Context:
         _check(load().tvs_quality(self._h, _dev(x, (n2, n1)), _dev(ref, (n2, n1), x.dtype), n2, n1,
                                   _dtype_code(x), out, _stream(x.device)))
         return {"psnr": out[0], "mssim": out[1], "mse": out[2]}
+
+    def set_tiles(self, run1=0, run1d=0, rows=0, cols=0, run2=0):
+        """Force workgroup shapes for later calls and jobs (0 = the tuner's)."""
+        _check(load().tvs_set_tiles(self._h, int(run1), int(run1d), int(rows), int(cols), int(run2)))
+
+    def get_tiles(self, shape, dtype, layout, h=1.0):
+        """The tuner's (run1, run1d, rows, cols, run2) for a problem shape,
+        zeros if not tuned yet."""
+        out = (ctypes.c_int * 5)()
+        code = TVS_F32 if dtype == torch.float32 else TVS_F64
+        _check(load().tvs_get_tiles(self._h, int(shape[0]), int(shape[1]), code, ctypes.byref(layout),
+                                    float(h), out))
+        return tuple(out)
 
     def quality_noalloc(self, x, ref):
         """As quality(), through tvs_quality_noalloc: the library allocates
