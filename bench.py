@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--inner", type=int, default=500)
     ap.add_argument("--no-compare", action="store_true", help="skip the float64 comparator solves")
+    ap.add_argument("--tiles", type=int, nargs=5, default=None, metavar=("RUN1", "RUN1D", "ROWS", "COLS", "RUN2"),
+                    help="force the workgroup shapes instead of tuning them (profiling runs: no tuning launches)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="host cores (worker processes) for the CPU oracle baseline, at most os.cpu_count()")
@@ -495,6 +497,8 @@ def main():
     delta, alpha = synth.params_for_sigma(args.sigma)
     _, d64 = synth.noisy_f32(n, n, args.sigma, 31)
     ctx = Context(0)
+    if args.tiles:
+        ctx.set_tiles(*args.tiles)
     dev = torch.device("cuda", 0)
     d0 = torch.tensor(d64, dtype=torch.float32, device=dev)
     tau = torch.empty((2, n + 1, n + 1), dtype=torch.float32, device=dev)
@@ -580,8 +584,8 @@ def main():
                      "copy_gbs": round(copy_bandwidth(), 1)},
         "kernels": breakdown,
     }
-    t1 = ctx.get_tiles((n, n), torch.float32, lay)
-    out["tiles"] = {"step1_update_run": t1[0], "step1_vecdiv_run": t1[1], "green_rows": t1[2],
+    t1 = tuple(args.tiles) if args.tiles else ctx.get_tiles((n, n), torch.float32, lay)
+    out["tiles"] = {"forced": bool(args.tiles), "step1_update_run": t1[0], "step1_vecdiv_run": t1[1], "green_rows": t1[2],
                     "green_cols": t1[3], "step2_update_run": t1[4]}
 
     if not args.no_compare:
