@@ -614,14 +614,15 @@ ShapeKey shape_key(int kind, int N2, int N1, double h, const tvs_layout* l) {
 template <typename T>
 void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream_t s) {
   Tiles& cached = c->tuned[key];
-  if (cached.run1 == 0) {
+  const Tiles& f = c->force;
+  const bool forced = f.run1 > 0 && f.run1d > 0 && (P.bdct || (f.rows > 0 && f.cols > 0));
+  if (cached.run1 == 0 && !forced) {
     const Tiles t = tune_step1<T>(P, s);
     cached.run1 = t.run1;
     cached.run1d = t.run1d;
     cached.rows = t.rows;
     cached.cols = t.cols;
   }
-  const Tiles& f = c->force;
   P.ss.sf.run = f.run1 > 0 ? f.run1 : cached.run1;
   P.ss.sf.run_div = f.run1d > 0 ? f.run1d : cached.run1d;
   if (!P.bdct) {
@@ -633,7 +634,7 @@ void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream
 template <typename T>
 void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream_t s) {
   Tiles& cached = c->tuned[key];
-  if (cached.run2 == 0) cached.run2 = tune_step2<T>(P, s);
+  if (cached.run2 == 0 && c->force.run2 <= 0) cached.run2 = tune_step2<T>(P, s);
   P.ss.sf.run = c->force.run2 > 0 ? c->force.run2 : cached.run2;
 }
 
