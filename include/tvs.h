@@ -276,6 +276,17 @@ int tvs_energy_history(tvs_ctx* ctx, double* out, int cap, int* n);
 enum { TVS_LP_IMAGE = 0, TVS_LP_BLOCKDCT = 1 };
 int tvs_set_local_projection(tvs_ctx* ctx, int kind);
 
+/* Grouping of the frequency blocks of TVS_LP_BLOCKDCT (eq. invLaplLowCapLong,
+ * Lemma lmChainOp): the frequency rows are cut into ceil(n2 / amax) blocks and
+ * the columns into ceil(n1 / bmax) blocks (amax x bmax the largest box, n2 x n1
+ * the grid of N2 + 1 x N1 + 1 points), and the sum over the blocks is taken g2
+ * row blocks by g1 column blocks at a time; the per-box workspace is g2 x g1
+ * blocks at most.  0 (the default) chooses each from the launch size, with
+ * at most 16 blocks per group; a positive value is cut to the block count.
+ * Applies to plans built after the call.  Results depend on the grouping
+ * through the order of the sums only.  TVS_EINVAL outside [0, 64]. */
+int tvs_set_block_groups(tvs_ctx* ctx, int g2, int g1);
+
 /* Workgroup shapes (performance only: every choice gives the same results,
  * bit for bit).  The first time a problem shape (dtype, image size, layout,
  * h; LP_m realisation) is built in a context, the library times candidate

@@ -47,7 +47,7 @@ def build(verbose=False, jobs=3):
     tmp = LIB + ".tmp"
     rocm_lib = os.path.join(os.path.dirname(os.path.dirname(hipcc())), "lib")
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + [
-        "-L", rocm_lib, "-lrocblas", "-Wl,-rpath," + rocm_lib]
+        "-L", rocm_lib, "-Wl,-rpath," + rocm_lib]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

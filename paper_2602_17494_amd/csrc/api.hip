@@ -73,7 +73,8 @@ using ShapeKey = std::tuple<int, int, int, double, int, int, int, int>;  // dtyp
 struct Tiles {
   int run1 = 0, run1d = 0, rows = 0, cols = 0, run2 = 0;
 };
-using ProbKey = std::tuple<int, int, double, int, int, int, int, int>;  // N2, N1, h, M2, M1, sy, sx, LP kind
+// N2, N1, h, M2, M1, sy, sx, LP kind, block groups (rows, columns) of the block-DCT plan
+using ProbKey = std::tuple<int, int, double, int, int, int, int, int, int, int>;
 
 struct SubSet {
   AxisLayout ay{}, ax{};
@@ -249,6 +250,7 @@ struct tvs_ctx {
   std::map<tvs::GridKey, std::unique_ptr<tvs::DevBuf>> projtmp;
   tvs::KernelTimer timer;
   int lp_kind = TVS_LP_IMAGE;  // realisation of LP_m for the one-shot Step-1 calls
+  int bd_g2 = 0, bd_g1 = 0;    // frequency blocks per group of the block-DCT plans (0: automatic)
   tvs::Tiles force;            // tvs_set_tiles: fields > 0 override the tuner
   std::map<tvs::ShapeKey, tvs::Tiles> tuned;  // the tuner's choices per problem shape
   std::vector<double> history;  // energies per sweep of the last one-shot step with statistics
@@ -386,7 +388,7 @@ std::unique_ptr<Step1Problem<T>> make_step1(tvs_ctx* c, int N2, int N1, double h
     std::vector<std::array<int, 4>> boxes;
     for (auto& d : P->ss.subs) boxes.push_back({d.i0, d.j0, d.bi, d.bj});
     if (lp_kind == TVS_LP_BLOCKDCT)
-      P->bdct = std::make_unique<BlockDctPlan<T>>(n2, n1, h, boxes, s);
+      P->bdct = std::make_unique<BlockDctPlan<T>>(n2, n1, h, boxes, s, c->bd_g2, c->bd_g1);
     else
       P->local = std::make_unique<GreenPlan<T>>(tab, boxes, s);
   }
@@ -441,7 +443,8 @@ void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream
 template <typename T>
 Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
-  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, c->lp_kind};
+  const bool bd = c->lp_kind == TVS_LP_BLOCKDCT;
+  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, c->lp_kind, bd ? c->bd_g2 : 0, bd ? c->bd_g1 : 0};
   auto& mp = s1map<T>(c);
   auto it = mp.find(key);
   Step1Problem<T>& ref = it != mp.end() ? *it->second : *(mp[key] = make_step1<T>(c, N2, N1, h, l, s, c->lp_kind));
@@ -452,7 +455,7 @@ Step1Problem<T>& get_step1(tvs_ctx* c, int N2, int N1, double h, const tvs_layou
 template <typename T>
 Step2Problem<T>& get_step2(tvs_ctx* c, int N2, int N1, double h, const tvs_layout* l, hipStream_t s) {
   if (!l) throw Error(TVS_EINVAL, "layout is NULL");
-  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, 0};
+  auto key = ProbKey{N2, N1, h, l->M2, l->M1, l->s_y, l->s_x, 0, 0, 0};
   auto& mp = s2map<T>(c);
   auto it = mp.find(key);
   Step2Problem<T>& ref = it != mp.end() ? *it->second : *(mp[key] = make_step2<T>(N2, N1, h, l, s));
@@ -1753,6 +1756,15 @@ int tvs_set_local_projection(tvs_ctx* ctx, int kind) {
     if (!ctx) throw Error(TVS_EINVAL, "NULL context");
     if (kind != TVS_LP_IMAGE && kind != TVS_LP_BLOCKDCT) throw Error(TVS_EINVAL, "unknown local projection");
     ctx->lp_kind = kind;
+  });
+}
+
+int tvs_set_block_groups(tvs_ctx* ctx, int g2, int g1) {
+  return guarded([&] {
+    if (!ctx) throw Error(TVS_EINVAL, "NULL context");
+    if (g2 < 0 || g1 < 0 || g2 > 64 || g1 > 64) throw Error(TVS_EINVAL, "block groups must be in [0, 64]");
+    ctx->bd_g2 = g2;
+    ctx->bd_g1 = g1;
   });
 }
 

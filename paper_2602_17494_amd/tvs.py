@@ -111,6 +111,8 @@ def load():
     lib.tvs_energy_history.restype = ci
     lib.tvs_set_local_projection.argtypes = [vp, ci]
     lib.tvs_set_local_projection.restype = ci
+    lib.tvs_set_block_groups.argtypes = [vp, ci, ci]
+    lib.tvs_set_block_groups.restype = ci
     lib.tvs_tangent_field.argtypes = [vp, vp, ci, ci, ci, cd, vp, vp]
     lib.tvs_tangent_field.restype = ci
     lib.tvs_quality.argtypes = [vp, vp, vp, ci, ci, ci, ctypes.POINTER(cd), vp]
@@ -133,7 +135,7 @@ EXPORTED = ["tvs_ctx_create", "tvs_ctx_destroy", "tvs_last_error", "tvs_ctx_byte
             "tvs_job_create", "tvs_batch_sweep", "tvs_job_status", "tvs_job_result",
             "tvs_job_bytes", "tvs_job_destroy", "tvs_job_export_state", "tvs_job_import_state",
             "tvs_tangent_field", "tvs_quality", "tvs_quality_noalloc", "tvs_set_local_projection",
-            "tvs_set_tiles", "tvs_get_tiles",
+            "tvs_set_block_groups", "tvs_set_tiles", "tvs_get_tiles",
             "tvs_energy_history"]
 
 
@@ -310,6 +312,11 @@ class Context:
         """TVS_LP_IMAGE (default) or TVS_LP_BLOCKDCT for the later one-shot
         Step-1 calls of this context."""
         _check(load().tvs_set_local_projection(self._h, int(kind)))
+
+    def set_block_groups(self, g2=0, g1=0):
+        """Frequency blocks per group (rows, columns) of the block-DCT plans
+        built later in this context; 0 chooses automatically."""
+        _check(load().tvs_set_block_groups(self._h, int(g2), int(g1)))
 
     def tangent_field(self, d, h=1.0, out=None):
         """tau_0 = (-D_y d, D_x d) with Neumann differences, 2 x (N2+1) x (N1+1)."""

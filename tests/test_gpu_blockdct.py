@@ -77,6 +77,56 @@ def test_blockdct_against_oracle_and_image_method(ctxs, n2, n1, lay, sweeps, inn
         assert np.abs(d - d_im).max() < 1e-4
 
 
+_ORACLE = {}
+
+
+def oracle_cached(d64, lay, sweeps, inner, key):
+    if key not in _ORACLE:
+        _ORACLE[key] = oracle(d64, lay, sweeps, inner)
+    return _ORACLE[key]
+
+
+# 8 x 8 layouts: 64 boxes and 7 x 7 or 6 x 8 frequency blocks, summed one
+# block at a time (every partial sum of W and O accumulates), in uneven
+# groups, and in the automatic grouping
+GROUP_CASES = [
+    (320, 320, (8, 8, 4, 4), (1, 1)),
+    (320, 320, (8, 8, 4, 4), (0, 0)),
+    (288, 352, (8, 8, 4, 4), (2, 3)),
+    (288, 352, (8, 8, 4, 4), (1, 1)),
+]
+
+
+@pytest.mark.parametrize("n2,n1,lay,groups", GROUP_CASES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_blockdct_frequency_groups_against_oracle(ctxs, n2, n1, lay, groups, dtype):
+    print(f"blockdct groups {groups} {n2}x{n1} layout={lay} {dtype}", flush=True)
+    bd, _ = ctxs
+    _, d64 = synth.noisy_f32(n2, n1, 0.1, 5)
+    bd.set_block_groups(*groups)
+    try:
+        d, tau, st = solve(bd, d64, dtype, lay, 1, 2)
+    finally:
+        bd.set_block_groups(0, 0)
+    d_ref, tau_ref, h1 = oracle_cached(d64, lay, 1, 2, (n2, n1, lay))
+    if dtype == torch.float64:
+        assert np.abs(tau - tau_ref).max() < 1e-10
+        assert np.abs(d - d_ref).max() < 1e-10
+        assert st[0]["energy"] == pytest.approx(h1[-1], rel=1e-10)
+    else:
+        assert np.abs(tau - tau_ref).max() < 1e-5
+        assert np.abs(d - d_ref).max() < 1e-4
+
+
+def test_block_groups_rejected_outside_range(ctxs):
+    from paper_2602_17494_amd import TvsError
+    bd, _ = ctxs
+    for g in ((-1, 0), (0, 65)):
+        with pytest.raises(TvsError) as e:
+            bd.set_block_groups(*g)
+        assert e.value.code == -1  # TVS_EINVAL
+
+
 def test_blockdct_512_reduced_counts(ctxs):
     """The 512 x 512 workload's 2 x 2 layout (8-pixel stripes) at 1 sweep x
     5 inner: float32 block-DCT against the float64 oracle."""
