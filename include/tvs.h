@@ -267,10 +267,13 @@ int tvs_energy_history(tvs_ctx* ctx, double* out, int cap, int* n);
  * subdomain:
  *   TVS_LP_IMAGE     (default) the inverse Laplacian of the whole grid on a
  *                    box through the image identity and box-sized FFTs
- *   TVS_LP_BLOCKDCT  the paper's block formula (eq. invLaplLowCapLong): the
- *                    DCT matrix columns of the box, the spectral diagonal of
- *                    the whole grid, four batched dense products per apply
- *                    (about 2 n2 n1 (box side) multiply-adds per box)
+ *   TVS_LP_BLOCKDCT  the paper's block formula (eq. invLaplLowCapLong): a
+ *                    sum over frequency blocks of products of DCT matrix
+ *                    blocks (the box's columns, the block's rows) and the
+ *                    spectral diagonal of the whole grid, on the matrix
+ *                    cores (about 2 n2 n1 (box side) multiply-adds per box;
+ *                    workspace of a few frequency blocks per box, see
+ *                    tvs_set_block_groups)
  * Both compute the same operator; results differ by rounding only.  Jobs
  * (tvs_job_*) always use TVS_LP_IMAGE.  TVS_EINVAL for another kind. */
 enum { TVS_LP_IMAGE = 0, TVS_LP_BLOCKDCT = 1 };

@@ -104,7 +104,7 @@ __device__ __forceinline__ void lds4(const double* p, double (&o)[4]) {
 
 // Z[b] (M x N) = A[b] (M x K) B[b] (K x N) for box b = blockIdx.z, one
 // (32 TB) x (32 TB) output tile per workgroup of four waves, each wave
-// owning TB x TB blocks of 16 x 16.  K advances in stages of 128 bytes per
+// owning TB x TB blocks of 16 x 16 (the plan launches TB = 2).  K advances in stages of 128 bytes per
 // row (32 floats or 16 doubles) through two LDS buffers: the next stage is
 // read from global memory (16-byte loads) into registers while the current
 // one feeds the matrix cores.  Both tiles are kept with k contiguous (A as
@@ -250,8 +250,9 @@ BlockDctPlan<T>::BlockDctPlan(int n2_, int n1_, double h, const std::vector<std:
   r2 = round4(n2);
   r1 = round4(n1);
   // frequency blocks no larger than the largest box, grouped so that the
-  // Y product of one group has about 4096 workgroups of 64 x 64, with at
-  // most 16 blocks per group
+  // Y product of one group has about 16384 workgroups of 64 x 64 (whole
+  // frequency rows first: the W product's inner dimension is the group's
+  // width), with at most 16 blocks per group
   nb2 = (r2 + amax - 1) / amax;
   nb1 = (r1 + bmax - 1) / bmax;
   e2_ = block_edges(r2, nb2);
@@ -260,9 +261,9 @@ BlockDctPlan<T>::BlockDctPlan(int n2_, int n1_, double h, const std::vector<std:
   auto y_wgs = [&](int a, int c) { return static_cast<long long>(nbox) * tiles_of(a * fa, 64) * tiles_of(c * fb, 64); };
   g1 = 1;
   g2 = 1;
-  while (g1 < nb1 && (g1 + 1) * g2 <= 16 && y_wgs(g2, g1) < 4096) ++g1;
+  while (g1 < nb1 && (g1 + 1) * g2 <= 16 && y_wgs(g2, g1) < 16384) ++g1;
   if (g1 == nb1)
-    while (g2 < nb2 && g1 * (g2 + 1) <= 16 && y_wgs(g2, g1) < 4096) ++g2;
+    while (g2 < nb2 && g1 * (g2 + 1) <= 16 && y_wgs(g2, g1) < 16384) ++g2;
   if (force_g2 > 0 || force_g1 > 0) {
     g2 = force_g2 > 0 ? std::min(force_g2, nb2) : g2;
     g1 = force_g1 > 0 ? std::min(force_g1, nb1) : g1;
@@ -270,15 +271,10 @@ BlockDctPlan<T>::BlockDctPlan(int n2_, int n1_, double h, const std::vector<std:
   rows_g_ = cols_g_ = 0;
   for (int r = 0; r < nb2; r += g2) rows_g_ = std::max(rows_g_, e2_[std::min(r + g2, nb2)] - e2_[r]);
   for (int c = 0; c < nb1; c += g1) cols_g_ = std::max(cols_g_, e1_[std::min(c + g1, nb1)] - e1_[c]);
-  // multiply-adds as launched (per box): U and O once per row group, Y and W
-  // once per block group
-  double per_box = 0;
-  for (int r = 0; r < nb2; r += g2) {
-    const double rows = e2_[std::min(r + g2, nb2)] - e2_[r];
-    per_box += 2.0 * rows * ap * bp;  // U and O
-    for (int c = 0; c < nb1; c += g1) per_box += 2.0 * rows * (e1_[std::min(c + g1, nb1)] - e1_[c]) * bp;
-  }
-  macs_ = per_box * nbox;
+  // multiply-adds of the formula on each box's own extents (ni x nj), over
+  // the whole frequency grid: U and O n2 ni nj each, Y and W n2 n1 nj each
+  macs_ = 0;
+  for (const auto& b : boxes) macs_ += 2.0 * n2 * double(b[2]) * b[3] + 2.0 * n2 * double(n1) * b[3];
 
   // the DCT matrices of both sides and their transposes (shared when the
   // sides agree), r x r with zeros beyond n, plus a zero tail: a 16-byte
@@ -340,18 +336,10 @@ void BlockDctPlan<T>::gemm(const BdOperand<T>& A, const BdOperand<T>& B, T* Z, l
                            int m, int n, int k, int mode, const T* lam, long long ldl, hipStream_t s) {
   if ((m | n | k) & 3) throw Error(-1, "internal: block-DCT product extents must be multiples of 4");
   const auto* bx = aboxes_d_.as<std::array<int, 4>>();
-  // 128 x 128 tiles unless they pad the work by more than 15 % or leave
-  // fewer than 512 workgroups
-  const double w64 = double(tiles_of(m, 64)) * tiles_of(n, 64) * 4096.0;
-  const double w128 = double(tiles_of(m, 128)) * tiles_of(n, 128) * 16384.0;
-  const long long wg128 = static_cast<long long>(nbox) * tiles_of(m, 128) * tiles_of(n, 128);
-  if (w128 <= 1.15 * w64 && wg128 >= 512) {
-    hipLaunchKernelGGL((k_bd_gemm<T, 4>), dim3(tiles_of(n, 128), tiles_of(m, 128), nbox), dim3(256), 0, s, bx, A, B,
-                       Z, ldz, zbs, m, n, k, mode, lam, ldl);
-  } else {
-    hipLaunchKernelGGL((k_bd_gemm<T, 2>), dim3(tiles_of(n, 64), tiles_of(m, 64), nbox), dim3(256), 0, s, bx, A, B,
-                       Z, ldz, zbs, m, n, k, mode, lam, ldl);
-  }
+  // 64 x 64 tiles: on these shapes (inner dimensions of a few hundred) the
+  // 128 x 128 tile ran 1.3 to 1.5 times slower for every grouping tried
+  hipLaunchKernelGGL((k_bd_gemm<T, 2>), dim3(tiles_of(n, 64), tiles_of(m, 64), nbox), dim3(256), 0, s, bx, A, B, Z,
+                     ldz, zbs, m, n, k, mode, lam, ldl);
   TVS_LAUNCH_CHECK();
 }
 

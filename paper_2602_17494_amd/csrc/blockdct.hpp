@@ -26,7 +26,7 @@
 //
 // Every product is a dense contraction and runs on the matrix cores through
 // one hand-written batched kernel (MFMA 16x16x4, float32 or float64 in and
-// out, LDS-staged 64 x 64 or 128 x 128 tiles, 16-byte global loads),
+// out, LDS-staged 64 x 64 tiles, 16-byte global loads),
 // launched over all boxes at once.  For those loads every table and
 // workspace row is a multiple of 4 elements long and zero beyond the data,
 // and each box is handled in a frame that starts at the multiple of 4 at or
@@ -69,8 +69,8 @@ class BlockDctPlan {
   void apply_div(const T* u, const Frame& uf, T* phi, const Frame& pf, hipStream_t s,
                  KernelTimer* timer = nullptr, const char* tag = "bdct");
   size_t bytes() const;
-  // multiply-adds of one apply (all boxes, padded extents as launched), for
-  // the FLOP roofline
+  // multiply-adds of one apply by the formula on the boxes' own extents
+  // (all boxes, padding excluded), for the FLOP roofline
   double macs() const { return macs_; }
 
   int n2, n1, nbox, amax, bmax;
