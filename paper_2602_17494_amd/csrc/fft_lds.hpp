@@ -56,6 +56,40 @@ __device__ __forceinline__ void dft4(cplx<T>& a, cplx<T>& b, cplx<T>& c, cplx<T>
   d = csub(d0, mi);
 }
 
+// Last stage of the radix-8 butterfly: the 4-point DFTs e of the even and o
+// of the odd inputs, o twiddled by w8^k, combined by 2-point DFTs.
+template <typename T>
+__device__ __forceinline__ void radix8_combine(cplx<T>* v, cplx<T> e0, cplx<T> e1, cplx<T> e2, cplx<T> e3,
+                                               cplx<T> o0, cplx<T> o1, cplx<T> o2, cplx<T> o3, bool inv) {
+  using C = cplx<T>;
+  const T h = T(0.70710678118654752440);
+  // forward w8 = (1 - i)/sqrt2, w8^2 = -i, w8^3 = (-1 - i)/sqrt2; the inverse conjugates
+  const C t1 = inv ? C{h * (o1.x - o1.y), h * (o1.x + o1.y)} : C{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+  const C t2 = inv ? C{-o2.y, o2.x} : C{o2.y, -o2.x};
+  const C t3 = inv ? C{-h * (o3.x + o3.y), h * (o3.x - o3.y)} : C{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+// The radix-8 butterfly when inputs 4..7 are zero (the first pass of a
+// transform of a sequence that is zero on its upper half): each 4-point DFT
+// has two non-zero inputs a, b and gives a + b, a -/+ i b, a - b, a +/- i b.
+// Equal to butterfly<8> on such inputs up to the sign of zero results.
+template <typename T>
+__device__ __forceinline__ void butterfly8_half(cplx<T>* v, bool inv) {
+  using C = cplx<T>;
+  const C m2 = inv ? C{-v[2].y, v[2].x} : C{v[2].y, -v[2].x};  // (+i or -i) v2, as in dft4
+  const C m3 = inv ? C{-v[3].y, v[3].x} : C{v[3].y, -v[3].x};
+  radix8_combine(v, cadd(v[0], v[2]), cadd(v[0], m2), csub(v[0], v[2]), csub(v[0], m2), cadd(v[1], v[3]),
+                 cadd(v[1], m3), csub(v[1], v[3]), csub(v[1], m3), inv);
+}
+
 template <int R, typename T>
 __device__ __forceinline__ void butterfly(cplx<T>* v, bool inv) {
   using C = cplx<T>;
@@ -88,19 +122,7 @@ __device__ __forceinline__ void butterfly(cplx<T>* v, bool inv) {
     C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
     dft4(e0, e1, e2, e3, inv);
     dft4(o0, o1, o2, o3, inv);
-    const T h = T(0.70710678118654752440);
-    // forward w8 = (1 - i)/sqrt2, w8^2 = -i, w8^3 = (-1 - i)/sqrt2; the inverse conjugates
-    const C t1 = inv ? C{h * (o1.x - o1.y), h * (o1.x + o1.y)} : C{h * (o1.x + o1.y), h * (o1.y - o1.x)};
-    const C t2 = inv ? C{-o2.y, o2.x} : C{o2.y, -o2.x};
-    const C t3 = inv ? C{-h * (o3.x + o3.y), h * (o3.x - o3.y)} : C{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
-    v[0] = cadd(e0, o0);
-    v[4] = csub(e0, o0);
-    v[1] = cadd(e1, t1);
-    v[5] = csub(e1, t1);
-    v[2] = cadd(e2, t2);
-    v[6] = csub(e2, t2);
-    v[3] = cadd(e3, t3);
-    v[7] = csub(e3, t3);
+    radix8_combine(v, e0, e1, e2, e3, o0, o1, o2, o3, inv);
   } else if constexpr (R == 9) {
     // 3-point DFTs of the stride-3 inputs, twiddles w9^(l k), then 3-point
     C y[3][3];
@@ -413,11 +435,15 @@ struct LdsSeqS {
   __device__ __forceinline__ void operator()(int s, int i, cplx<T> v) const { p[lds_swz(s * STRIDE + i)] = v; }
 };
 
-template <typename T, int NT, typename D, int P, typename LD, typename ST>
+// HALF (pass 0 of a radix-8 first pass only): the sequence is zero from
+// half its length on, so inputs t >= 4 of every butterfly are zero and are
+// neither loaded nor added.
+template <typename T, int NT, typename D, int P, bool HALF = false, typename LD, typename ST>
 __device__ __forceinline__ void fft_pass_s(LD& ld, ST& st, int batch, const cplx<T>* __restrict__ tw, bool inv) {
   using C = cplx<T>;
   constexpr int R = D::template radix<P>(), NBF = D::template nbf<P>(), LS = D::template ls<P>(),
                 TWS = D::template twstep<P>();
+  static_assert(!HALF || (P == 0 && R == 8), "the half-input pass is the radix-8 first pass");
   const int total = NBF * batch;
   for (int jj = threadIdx.x; jj < total; jj += NT) {
     const int b = jj / NBF;
@@ -425,17 +451,23 @@ __device__ __forceinline__ void fft_pass_s(LD& ld, ST& st, int batch, const cplx
     const int g = j / LS;
     const int k = j - g * LS;
     C v[R];
+    if constexpr (HALF) {
 #pragma unroll
-    for (int t = 0; t < R; ++t) v[t] = ld(b, j + t * NBF, t);
-    if constexpr (LS > 1) {
+      for (int t = 0; t < R / 2; ++t) v[t] = ld(b, j + t * NBF, t);
+      butterfly8_half<T>(v, inv);
+    } else {
 #pragma unroll
-      for (int t = 1; t < R; ++t) {
-        C w = tw[k * (t * TWS)];
-        if (inv) w.y = -w.y;
-        v[t] = cmul(v[t], w);
+      for (int t = 0; t < R; ++t) v[t] = ld(b, j + t * NBF, t);
+      if constexpr (LS > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          C w = tw[__mul24(k, t * TWS)];  // k < LS, so the 24-bit product is exact
+          if (inv) w.y = -w.y;
+          v[t] = cmul(v[t], w);
+        }
       }
+      butterfly<R, T>(v, inv);
     }
-    butterfly<R, T>(v, inv);
     const int base = g * (LS * R) + k;
 #pragma unroll
     for (int t = 0; t < R; ++t) st(b, base + t * LS, v[t]);
@@ -453,32 +485,33 @@ __device__ __forceinline__ void fft_run_tail_s(ST& last, cplx<T>* p0, cplx<T>* p
   fft_pass_s<T, NT, D, 2>(b, last, batch, tw, inv);
 }
 
-template <typename T, int NT, typename D, typename LD, typename ST>
+template <typename T, int NT, typename D, bool HALF0 = false, typename LD, typename ST>
 __device__ __forceinline__ void fft_run_s(LD& first, ST& last, cplx<T>* p0, cplx<T>* p1, int batch,
                                           const cplx<T>* __restrict__ tw, bool inv) {
   {
     LdsSeqS<T, D::n> o{p0};
-    fft_pass_s<T, NT, D, 0>(first, o, batch, tw, inv);
+    fft_pass_s<T, NT, D, 0, HALF0>(first, o, batch, tw, inv);
   }
   __syncthreads();
   fft_run_tail_s<T, NT, D>(last, p0, p1, batch, tw, inv);
 }
 
-// as fft_run_to_lds: the result (in p0, three passes) ends with a barrier
-template <typename T, int NT, typename D, typename LD>
+// as fft_run_to_lds: the result (in p0, three passes) ends with a barrier;
+// HALF0: the input sequences are zero from half their length on
+template <typename T, int NT, typename D, bool HALF0 = false, typename LD>
 __device__ __forceinline__ cplx<T>* fft_run_to_lds_s(LD& first, cplx<T>* p0, cplx<T>* p1, int batch,
                                                      const cplx<T>* __restrict__ tw, bool inv) {
   LdsSeqS<T, D::n> o{p0};
-  fft_run_s<T, NT, D>(first, o, p0, p1, batch, tw, inv);
+  fft_run_s<T, NT, D, HALF0>(first, o, p0, p1, batch, tw, inv);
   __syncthreads();
   return p0;
 }
 
-template <typename T, int NT, typename D>
+template <typename T, int NT, typename D, bool HALF0 = false>
 __device__ __forceinline__ cplx<T>* fft_lds_s(cplx<T>* a, cplx<T>* bbuf, int batch, const cplx<T>* __restrict__ tw,
                                               bool inv) {
   LdsSeqS<T, D::n> in{a};
-  return fft_run_to_lds_s<T, NT, D>(in, bbuf, a, batch, tw, inv);
+  return fft_run_to_lds_s<T, NT, D, HALF0>(in, bbuf, a, batch, tw, inv);
 }
 
 }  // namespace tvs

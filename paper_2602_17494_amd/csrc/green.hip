@@ -347,9 +347,14 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   if (2 * q0 >= bx.ni) return;  // whole workgroup idle for this box
   const C* tw = stage_twiddles<T, NT, TWL>(buf + 2 * lds_round(ppw * Lj), d.tw_j, Lj);
   // all NT threads stage the packed rows (the first pass has fewer butterflies
-  // than threads, and these loads are the latency-bound part)
-  for (int e = threadIdx.x; e < ppw * Lj; e += NT) {
-    const int qq = d.fd_Lj.div(e), c = e - qq * Lj;
+  // than threads, and these loads are the latency-bound part).  With a
+  // compile-time length only the first half of each row is staged: a box
+  // row has at most L/2 points (L >= 2 nj - 1 and even), and the half-input
+  // first pass reads no more.
+  constexpr int kHalf = SL ? SL / 2 : 1;
+  const int Lst = SL ? kHalf : Lj;
+  for (int e = threadIdx.x; e < ppw * Lst; e += NT) {
+    const int qq = SL ? e / kHalf : d.fd_Lj.div(e), c = e - qq * Lst;
     const int ra = 2 * (q0 + qq), rb = ra + 1;
     T va = T(0), vb = T(0);
     if (c < bx.nj) {
@@ -361,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
   __syncthreads();
   const C* res;
   if constexpr (SL != 0)
-    res = fft_lds_s<T, NT, FftOf<SL>>(buf, buf + lds_round(ppw * Lj), ppw, tw, false);
+    res = fft_lds_s<T, NT, FftOf<SL>, true>(buf, buf + lds_round(ppw * Lj), ppw, tw, false);
   else if constexpr (OB)
     res = fft_lds_1b<T, NT>(buf, d.fj, Lj, ppw, tw, false);
   else
@@ -418,7 +423,7 @@ __device__ __forceinline__ void cols_prefetched(const GreenDev<T>& d, LD& ld_s, 
   }
   const C* X;
   if constexpr (SL != 0)
-    X = fft_run_to_lds_s<T, NT, FftOf<SL>>(ld_s, bufa, bufb, cpw, tw, false);
+    X = fft_run_to_lds_s<T, NT, FftOf<SL>, true>(ld_s, bufa, bufb, cpw, tw, false);  // box rows <= Li / 2
   else
     X = fft_run_to_lds<T, NT>(d.fi, ld_s, bufa, bufb, Li, cpw, tw, false);
   C* Y = (X == bufa) ? bufb : bufa;
@@ -584,9 +589,39 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
       if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
     }
   };
-  if constexpr (SL != 0)
-    fft_run_s<T, NT, FftOf<SL>>(ld, st, buf, buf + lds_round(ppw * Lj), ppw, tw, true);
-  else if constexpr (OB)
+  if constexpr (SL != 0) {
+    // Stage the packed inputs of the ppw row pairs in the second LDS buffer
+    // before the first pass (which then reads LDS): the two rows of a pair
+    // are adjacent in a half-spectrum column, so one 16-byte load gives both
+    // at frequency kk (and, mirrored, at Lj - kk), and consecutive lanes read
+    // consecutive pairs, 128 contiguous bytes per column for 8 pairs, where
+    // the first pass would read one element per lane, a column apart.
+    C* stg = buf + lds_round(ppw * Lj);
+    for (int e = threadIdx.x; e < (half + 1) * ppw; e += NT) {
+      const int kk = d.fd_ppw.div(e), qq = e - kk * ppw;
+      const int ra = 2 * (q0 + qq);
+      C a{T(0), T(0)}, c{T(0), T(0)};
+      if (ra < bx.ni) {
+        // rows ra and ra + 1 (the column holds scol > ni rows, so the second
+        // is inside it; it is zero past the box)
+        const C* col = S + static_cast<size_t>(kk) * scol + ra;
+        if constexpr (sizeof(T) == 4) {
+          const float4 v = *reinterpret_cast<const float4*>(col);  // 16-byte aligned: scol and ra even
+          a = C{T(v.x), T(v.y)};
+          c = C{T(v.z), T(v.w)};
+        } else {
+          a = col[0];
+          c = col[1];
+        }
+        if (ra + 1 >= bx.ni) c = C{T(0), T(0)};
+      }
+      stg[lds_swz(qq * Lj + kk)] = C{a.x - c.y, a.y + c.x};
+      if (kk != 0 && kk != half) stg[lds_swz(qq * Lj + Lj - kk)] = C{a.x + c.y, c.x - a.y};
+    }
+    __syncthreads();
+    LdsSeqS<T, SL> first{stg};
+    fft_run_s<T, NT, FftOf<SL>>(first, st, buf, stg, ppw, tw, true);
+  } else if constexpr (OB)
     fft_run_1b<T, NT>(d.fj, ld, st, buf, Lj, ppw, tw, true);
   else
     fft_run<T, NT>(d.fj, ld, st, buf, buf + lds_round(ppw * Lj), Lj, ppw, tw, true);
