@@ -379,8 +379,19 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
     const C z = res[lds_swz(qq * Lj + k)];
     const C zn = res[lds_swz(qq * Lj + (k == 0 ? 0 : Lj - k))];
     C* col = S + static_cast<size_t>(k) * scol;
-    if (ra < bx.ni) col[ra] = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
-    if (rb < bx.ni) col[rb] = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
+    const C va = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
+    const C vb = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
+    if constexpr (sizeof(T) == 4 && SL != 0) {
+      // both rows of the pair with one 16-byte store (adjacent in the
+      // column; 16-byte aligned: scol and ra even)
+      if (rb < bx.ni)
+        *reinterpret_cast<float4*>(col + ra) = make_float4(va.x, va.y, vb.x, vb.y);
+      else if (ra < bx.ni)
+        col[ra] = va;
+    } else {
+      if (ra < bx.ni) col[ra] = va;
+      if (rb < bx.ni) col[rb] = vb;
+    }
   }
 }
 
