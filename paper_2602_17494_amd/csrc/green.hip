@@ -381,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_fwd(GreenDev<T> d, const T* _
     C* col = S + static_cast<size_t>(k) * scol;
     const C va = C{T(0.5) * (z.x + zn.x), T(0.5) * (z.y - zn.y)};
     const C vb = C{T(0.5) * (z.y + zn.y), T(0.5) * (zn.x - z.x)};
-    if constexpr (sizeof(T) == 4 && SL != 0) {
+    if constexpr (sizeof(T) == 4) {
       // both rows of the pair with one 16-byte store (adjacent in the
       // column; 16-byte aligned: scol and ra even)
       if (rb < bx.ni)
@@ -600,13 +600,14 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
       if (rb < bx.ni) out[static_cast<long long>(rb) * pf.pitch + c] = z.y;
     }
   };
-  if constexpr (SL != 0) {
+  if constexpr (!OB) {
     // Stage the packed inputs of the ppw row pairs in the second LDS buffer
     // before the first pass (which then reads LDS): the two rows of a pair
     // are adjacent in a half-spectrum column, so one 16-byte load gives both
     // at frequency kk (and, mirrored, at Lj - kk), and consecutive lanes read
     // consecutive pairs, 128 contiguous bytes per column for 8 pairs, where
-    // the first pass would read one element per lane, a column apart.
+    // the first pass would read one element per lane, a column apart.  (The
+    // second buffer is first written by the second pass, after a barrier.)
     C* stg = buf + lds_round(ppw * Lj);
     for (int e = threadIdx.x; e < (half + 1) * ppw; e += NT) {
       const int kk = d.fd_ppw.div(e), qq = e - kk * ppw;
@@ -630,12 +631,16 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
       if (kk != 0 && kk != half) stg[lds_swz(qq * Lj + Lj - kk)] = C{a.x + c.y, c.x - a.y};
     }
     __syncthreads();
-    LdsSeqS<T, SL> first{stg};
-    fft_run_s<T, NT, FftOf<SL>>(first, st, buf, stg, ppw, tw, true);
-  } else if constexpr (OB)
+    if constexpr (SL != 0) {
+      LdsSeqS<T, SL> first{stg};
+      fft_run_s<T, NT, FftOf<SL>>(first, st, buf, stg, ppw, tw, true);
+    } else {
+      LdsSeq<T> first{stg, Lj};
+      fft_run<T, NT>(d.fj, first, st, buf, stg, Lj, ppw, tw, true);
+    }
+  } else {
     fft_run_1b<T, NT>(d.fj, ld, st, buf, Lj, ppw, tw, true);
-  else
-    fft_run<T, NT>(d.fj, ld, st, buf, buf + lds_round(ppw * Lj), Lj, ppw, tw, true);
+  }
 }
 
 // ---------------------------------------------------------------------------
