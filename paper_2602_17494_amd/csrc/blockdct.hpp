@@ -46,7 +46,9 @@ namespace tvs {
 //   p[off + b * bs + r0(b) * ro + c0(b) * co + i * ld + k],
 // and reads as zero unless i < lim(rk, rv) and k < lim(ck, cv), where a
 // limit kind of 0 is the fixed value, 1 the box's row count, 2 its column
-// count.
+// count.  Columns are read 16 bytes at a time, so off, the strides, ld and
+// the column limit must be multiples of 4 (the plan uses fixed column
+// limits only); a row limit may be any value.
 template <typename T>
 struct BdOperand {
   const T* p;
