@@ -180,6 +180,32 @@ def inv_laplacian(d, h=1.0):
     return idct2(inv_lambda(n2, n1, h) * dct2(d))
 
 
+def inv_laplacian_blocks(d_a, box_a, box_b, shape, row_blocks, col_blocks, h=1.0):
+    """R_B (Delta)^dagger E_A d by the block formula of eq. invLaplLowCapLong
+    (Section 6.2.2).  row_blocks and col_blocks are disjoint decompositions
+    of the frequency rows [0, n2) and columns [0, n1) into half-open ranges
+    (the blocks A-tilde_lambda of eq. def:2DDs are their products); box_a,
+    box_b = (i0, i1, j0, j1) are A_k and B_m.  The result is the sum over
+    lambda = (lambda2, lambda1) of
+        [C_{N2}]_{lambda2,B}^T  Lambda_lambda o ([C_{N2}]_{lambda2,A} d [C_{N1}]_{lambda1,A}^T)  [C_{N1}]_{lambda1,B},
+    where [C]_{l,A} holds the rows of frequency block l and the columns of A
+    (Figure fig:matvisualization) and Lambda_lambda is the block of the
+    diagonal of eq. form:DiscInvLaplTild on A-tilde_lambda; the middle factor
+    is diagonal, so of the double sum over lambda, lambda' in eq.
+    locglobprojpart3 only lambda' = lambda remains."""
+    n2, n1 = shape
+    c2, c1 = dct_matrix(n2), dct_matrix(n1)
+    lam = inv_lambda(n2, n1, h)
+    ai0, ai1, aj0, aj1 = box_a
+    bi0, bi1, bj0, bj1 = box_b
+    out = np.zeros((bi1 - bi0, bj1 - bj0))
+    for r0, r1 in row_blocks:
+        for q0, q1 in col_blocks:
+            forward = c2[r0:r1, ai0:ai1] @ d_a @ c1[q0:q1, aj0:aj1].T
+            out += c2[r0:r1, bi0:bi1].T @ (lam[r0:r1, q0:q1] * forward) @ c1[q0:q1, bj0:bj1]
+    return out
+
+
 def project_k(u, h=1.0):
     """Orthogonal projection onto K^h = null(div) on the grid of u (eq.
     formula:PKh): P u = u - grad (Delta)^dagger div u.  u has shape

@@ -140,3 +140,49 @@ def test_rotated_gradient_is_divergence_free_inside():
 def test_grow_box():
     assert op.grow_box((0, 4, 2, 5), (10, 10)) == (0, 5, 2, 6)
     assert op.grow_box((6, 10, 7, 10), (10, 10)) == (6, 10, 7, 10)
+
+
+def _random_cuts(rng, n):
+    """A random disjoint decomposition of [0, n) into half-open ranges."""
+    k = int(rng.integers(1, min(n, 6) + 1))
+    cuts = np.sort(rng.choice(np.arange(1, n), size=k - 1, replace=False)) if k > 1 else np.array([], int)
+    edges = [0] + [int(c) for c in cuts] + [n]
+    return list(zip(edges[:-1], edges[1:]))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_block_formula_is_restricted_inverse_laplacian(seed):
+    """Eq. invLaplLowCapLong summed over random disjoint frequency blocks,
+    with data on a box A read on another box B, equals the definition
+    R_B (Delta)^dagger E_A d on non-square grids.  A != B and unequal block
+    sizes make a transposed or swapped DCT block, or A's columns used on the
+    output side, fail."""
+    rng = np.random.default_rng(70 + seed)
+    n2, n1 = int(rng.integers(7, 23)), int(rng.integers(7, 23))
+    while n1 == n2:
+        n1 = int(rng.integers(7, 23))
+
+    def box():
+        i0, j0 = int(rng.integers(0, n2 - 2)), int(rng.integers(0, n1 - 2))
+        return (i0, int(rng.integers(i0 + 1, n2 + 1)), j0, int(rng.integers(j0 + 1, n1 + 1)))
+
+    a, b = box(), box()
+    d_a = rng.standard_normal((a[1] - a[0], a[3] - a[2]))
+    h = float(rng.choice([1.0, 0.5]))
+    ref = op.restrict(op.inv_laplacian(op.extend(d_a, a, (n2, n1)), h), b)
+    got = op.inv_laplacian_blocks(d_a, a, b, (n2, n1), _random_cuts(rng, n2), _random_cuts(rng, n1), h)
+    assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_block_formula_single_block_and_single_frequencies():
+    """The two extreme decompositions, one block and one block per frequency,
+    give the same operator."""
+    rng = np.random.default_rng(77)
+    n2, n1 = 11, 16
+    a, b = (2, 9, 3, 12), (0, 6, 5, 16)
+    d_a = rng.standard_normal((7, 9))
+    one = op.inv_laplacian_blocks(d_a, a, b, (n2, n1), [(0, n2)], [(0, n1)])
+    each = op.inv_laplacian_blocks(d_a, a, b, (n2, n1), [(i, i + 1) for i in range(n2)],
+                                   [(j, j + 1) for j in range(n1)])
+    ref = op.restrict(op.inv_laplacian(op.extend(d_a, a, (n2, n1))), b)
+    assert np.abs(one - ref).max() < 1e-12 and np.abs(each - ref).max() < 1e-12
