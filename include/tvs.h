@@ -291,9 +291,14 @@ int tvs_set_local_projection(tvs_ctx* ctx, int kind);
 int tvs_set_block_groups(tvs_ctx* ctx, int g2, int g1);
 
 /* Workgroup shapes (performance only: every choice gives the same results,
- * bit for bit).  The first time a problem shape (dtype, image size, layout,
- * h; LP_m realisation) is built in a context, the library times candidate
- * shapes on the problem's buffers and keeps the fastest for that shape:
+ * bit for bit).  The first time a one-shot call (tvs_step1, tvs_step2,
+ * tvs_schwarz_solve) builds a problem shape (dtype, image size, layout, h;
+ * LP_m realisation) in a context, the library times candidate shapes on the
+ * problem's buffers and keeps the fastest for that shape.  A job
+ * (tvs_job_create) times nothing: it takes the shapes forced or tuned before
+ * for its problem shape in the context, else the plans' defaults (a
+ * server's requests come in many sizes, and each would pay the tuning).
+ * The shapes:
  *   run1, run1d, run2  rows per thread of the Step-1 update, the Step-1
  *               vecdiv and the Step-2 update kernels (1, 2 or 4)
  *   rows, cols  targets for the row pairs per row-pass workgroup and the

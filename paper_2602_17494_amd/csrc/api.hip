@@ -435,9 +435,9 @@ std::unique_ptr<Step2Problem<T>> make_step2(int N2, int N1, double h, const tvs_
 
 ShapeKey shape_key(int kind, int N2, int N1, double h, const tvs_layout* l);
 template <typename T>
-void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream_t s);
+void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream_t s, bool tune = true);
 template <typename T>
-void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream_t s);
+void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream_t s, bool tune = true);
 
 // problems cached in the context by shape (the one-shot calls)
 template <typename T>
@@ -613,21 +613,27 @@ ShapeKey shape_key(int kind, int N2, int N1, double h, const tvs_layout* l) {
 }
 
 // The workgroup shapes of a Step-1 problem: forced, cached for its shape, or
-// tuned now (and cached).
+// tuned now (and cached).  With tune = false (jobs) nothing is timed: a shape
+// neither forced nor tuned before keeps the plan's defaults, which are tiles
+// of the same kernel path, so the results are the same bit for bit.
 template <typename T>
-void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream_t s) {
-  Tiles& cached = c->tuned[key];
+void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream_t s, bool tune) {
   const Tiles& f = c->force;
   const bool forced = f.run1 > 0 && f.run1d > 0 && (P.bdct || (f.rows > 0 && f.cols > 0));
-  if (cached.run1 == 0 && !forced) {
+  Tiles cached{};
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) cached = it->second;
+  if (cached.run1 == 0 && !forced && tune) {
     const Tiles t = tune_step1<T>(P, s);
-    cached.run1 = t.run1;
-    cached.run1d = t.run1d;
-    cached.rows = t.rows;
-    cached.cols = t.cols;
+    Tiles& entry = c->tuned[key];
+    entry.run1 = t.run1;
+    entry.run1d = t.run1d;
+    entry.rows = t.rows;
+    entry.cols = t.cols;
+    cached = entry;
   }
-  P.ss.sf.run = f.run1 > 0 ? f.run1 : cached.run1;
-  P.ss.sf.run_div = f.run1d > 0 ? f.run1d : cached.run1d;
+  if (f.run1 > 0 || cached.run1 > 0) P.ss.sf.run = f.run1 > 0 ? f.run1 : cached.run1;
+  if (f.run1d > 0 || cached.run1d > 0) P.ss.sf.run_div = f.run1d > 0 ? f.run1d : cached.run1d;
   if (!P.bdct) {
     GreenPlan<T>& gp = P.plain ? *P.global : *P.local;
     const int rows = f.rows > 0 ? f.rows : cached.rows, cols = f.cols > 0 ? f.cols : cached.cols;
@@ -635,10 +641,12 @@ void apply_tiles1(tvs_ctx* c, Step1Problem<T>& P, const ShapeKey& key, hipStream
   }
 }
 template <typename T>
-void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream_t s) {
-  Tiles& cached = c->tuned[key];
-  if (cached.run2 == 0 && c->force.run2 <= 0) cached.run2 = tune_step2<T>(P, s);
-  P.ss.sf.run = c->force.run2 > 0 ? c->force.run2 : cached.run2;
+void apply_tiles2(tvs_ctx* c, Step2Problem<T>& P, const ShapeKey& key, hipStream_t s, bool tune) {
+  int run2 = 0;
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) run2 = it->second.run2;
+  if (run2 == 0 && c->force.run2 <= 0 && tune) run2 = c->tuned[key].run2 = tune_step2<T>(P, s);
+  if (c->force.run2 > 0 || run2 > 0) P.ss.sf.run = c->force.run2 > 0 ? c->force.run2 : run2;
 }
 
 struct Host64 {
@@ -1156,8 +1164,11 @@ void job_create(tvs_ctx* c, tvs_job* j, const T* d0, hipStream_t s,
   st->p1 = make_step1<T>(c, N2, N1, j->prm.h, &j->lay, s, TVS_LP_IMAGE, false);
   st->p2 = make_step2<T>(N2, N1, j->prm.h, &j->lay, s);
   const ShapeKey sk = shape_key(int(dtype_of<T>()), N2, N1, j->prm.h, &j->lay);
-  apply_tiles1<T>(c, *st->p1, sk, s);
-  apply_tiles2<T>(c, *st->p2, sk, s);
+  // a job uses the shapes forced or tuned before for its problem shape and
+  // times none itself: the requests of a server come in many sizes, and each
+  // would pay the tuning (0.5 s for a 4096^2 float64 single-domain job)
+  apply_tiles1<T>(c, *st->p1, sk, s, false);
+  apply_tiles2<T>(c, *st->p2, sk, s, false);
   TVS_HIP(hipMemcpyAsync(st->d0.p, d0, esz * size_t(N2) * N1, kind, s));
   st->r1 = std::make_unique<Step1Run<T>>(*st->p1, st->d0.template as<T>(), N2, N1, &j->prm, &j->lay, &j->its,
                                          Partials{st->part.template as<double>(), 1024}, st->e1.template as<double>(), &c->timer);
