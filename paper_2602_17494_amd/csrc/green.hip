@@ -615,7 +615,7 @@ __global__ __launch_bounds__(NT) void k_green_rows_inv(GreenDev<T> d, T* __restr
       C a{T(0), T(0)}, c{T(0), T(0)};
       if (ra < bx.ni) {
         // rows ra and ra + 1 (the column holds scol > ni rows, so the second
-        // is inside it; it is zero past the box)
+        // is inside it; past the box it holds no data and is replaced by zero)
         const C* col = S + static_cast<size_t>(kk) * scol + ra;
         if constexpr (sizeof(T) == 4) {
           const float4 v = *reinterpret_cast<const float4*>(col);  // 16-byte aligned: scol and ra even
