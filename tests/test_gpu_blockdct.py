@@ -165,3 +165,38 @@ def test_unknown_local_projection_rejected(ctxs):
     with pytest.raises(TvsError) as e:
         bd.set_local_projection(7)
     assert e.value.code == -1  # TVS_EINVAL
+
+
+@pytest.mark.parametrize("dtype,tol_d,tol_tau", [(torch.float64, 1e-10, 1e-10), (torch.float32, 1e-4, 1e-5)])
+def test_blockdct_2048_reduced_counts_against_oracle(ctxs, dtype, tol_d, tol_tau):
+    """The 2048 x 2048 workload's 8 x 8 layout with the block formula in its
+    automatic grouping (2 x 8 frequency blocks per group, 4 row groups whose
+    partial sums accumulate), at 2 sweeps x 2 inner against the FP64 oracle's
+    stored values (tests/golden/make_golden_2048.py, sigma = 0.1)."""
+    import os
+    from paper_2602_17494_amd import make_iters, make_layout, make_params
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_2048_s2i2_sigma0.1.npz")
+    g = np.load(golden)
+    meta = g["meta"]
+    n = 2048
+    print(f"blockdct 2048 golden {dtype}", flush=True)
+    bd, _ = ctxs
+    _, d64 = synth.noisy_f32(n, n, 0.1, int(meta[1]))
+    delta, alpha = synth.params_for_sigma(0.1)
+    d0 = torch.tensor(d64, dtype=dtype, device=DEV)
+    tau = torch.empty((2, n + 1, n + 1), dtype=dtype, device=DEV)
+    d, st = bd.schwarz_solve(d0, make_params(delta, alpha), make_layout(8, 8, 16, 16),
+                             make_iters(int(meta[2]), int(meta[3])), tau_out=tau)
+    torch.cuda.synchronize()
+    d = d.double().cpu().numpy()
+    tau = tau.double().cpu().numpy()
+    ii, jj = g["ii"], g["jj"]
+    assert np.abs(tau[0, ii, jj] - g["tau1"]).max() < tol_tau
+    assert np.abs(tau[1, ii, jj] - g["tau2"]).max() < tol_tau
+    assert np.abs(d[np.minimum(ii, n - 1), np.minimum(jj, n - 1)] - g["d"]).max() < tol_d
+    w0 = int(g["win0"])
+    w = slice(w0, w0 + g["d_win"].shape[0])
+    assert np.abs(d[w, w] - g["d_win"]).max() < tol_d
+    assert np.abs(tau[:, w, w] - g["tau_win"]).max() < tol_tau
+    assert np.abs(d.sum(axis=1) - g["d_rowsum"]).max() < tol_d * n
+    assert np.abs(tau[1].sum(axis=1) - g["tau2_rowsum"]).max() < tol_tau * n
